@@ -1,0 +1,215 @@
+/*
+ * ovl.h - C ABI of the MI355X overlap-operator library (libovl.so).
+ *
+ * Hot path of arXiv:1106.4964 ("Efficient implementation of the overlap
+ * operator on multi-GPUs"): the Wilson dslash D_w (Sec. II, eq. 1-2) applied
+ * inside the Chebyshev/Clenshaw polynomial approximation of sign(H_w),
+ * H_w = gamma5 D_w(-rho) (eq. 4-5, Sec. V), with low-mode projection
+ * (eq. 6-7), the overlap operator D(m) (eq. 3, 8) and CG for propagators
+ * (Sec. II, Sec. V).  The whole periodic lattice lives on one GPU.
+ *
+ * Conventions
+ *  - Every call returns int: OVL_OK (0), a positive warning, or a negative
+ *    error.  ovl_last_error() gives a thread-local message for the last
+ *    failure.  Nothing throws across this ABI.
+ *  - Field buffers are caller-owned device memory; the library never frees
+ *    them or keeps them past the call, except the eigenvector buffer lent
+ *    to ovl_lowmodes_create (borrowed for the handle's lifetime).
+ *  - Handles (geometry, gauge, sign, lowmodes, net) are library-owned and
+ *    released with their _destroy call.
+ *  - All device work is enqueued on the caller's HIP stream.  Calls that
+ *    return host values (reductions, solvers, bounds) synchronise it.
+ *  - Lattice: dims = {Lx, Ly, Lz, Lt}, every extent even and >= 2,
+ *    periodic in all directions.  Site order: lex = x + Lx*(y + Ly*(z + Lz*t)),
+ *    parity p = (x+y+z+t) mod 2, even-odd index eo = p*N/2 + lex/2.
+ *    Gamma matrices: chiral basis, gamma5 = diag(1,1,-1,-1),
+ *    gamma_k = [[0,-i sigma_k],[i sigma_k,0]], gamma_4 = [[0,1],[1,0]].
+ *
+ * Device field layouts (part of the ABI)
+ *  A spinor is 12 complex numbers per site, complex index c = 3*spin + colour.
+ *  It is stored as 16-byte blocks, structure-of-arrays over the N/2 sites of
+ *  each parity:  [parity][block][N/2][16 bytes], where a block holds
+ *    OVL_F64  : 1 complex  (double re, im)        -> 12 blocks
+ *    OVL_F32  : 2 complex  (c = 2j, 2j+1)          ->  6 blocks
+ *    OVL_F16/OVL_BF16 : 4 complex (c = 4j..4j+3)   ->  3 blocks
+ *  A batch of nrhs spinors is nrhs such vectors back to back.
+ *  The canonical host/device AoS layout used by pack/unpack is complex128
+ *  [nrhs][N (lex order)][4 spin][3 colour].  Gauge fields enter as complex128
+ *  [N (lex)][4 mu][3][3] with U_mu(x) on the link x -> x + mu.
+ */
+#ifndef OVL_H
+#define OVL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void* ovl_stream_t; /* a hipStream_t (0 = null stream) */
+
+enum {
+  OVL_OK = 0,
+  OVL_W_NOT_CONVERGED = 1, /* solver stopped at maxiter; stats are valid   */
+  OVL_E_ARG = -1,          /* null pointer, bad size or out-of-range value */
+  OVL_E_DIMS = -2,         /* lattice extent odd or < 2                    */
+  OVL_E_PRECISION = -3,    /* precision/representation not available       */
+  OVL_E_ALIAS = -4,        /* output aliases an input that it may not      */
+  OVL_E_HIP = -5,          /* HIP runtime error (message has details)      */
+  OVL_E_NOT_SU3 = -6,      /* 12-real compression asked for non-SU(3) link */
+  OVL_E_BREAKDOWN = -7,    /* Krylov breakdown (p^dag A p <= 0)            */
+  OVL_E_NAN = -8,          /* NaN or Inf in an input or an iterate         */
+  OVL_E_NOMEM = -9,        /* device allocation failed                     */
+  OVL_E_STATE = -10        /* handle used in an invalid state              */
+};
+
+typedef enum { OVL_F64 = 0, OVL_F32 = 1, OVL_F16 = 2, OVL_BF16 = 3 } ovl_prec;
+
+#define OVL_MAX_RHS 12
+
+typedef struct ovl_geom ovl_geom;
+typedef struct ovl_gauge ovl_gauge;
+typedef struct ovl_sign ovl_sign;
+typedef struct ovl_lowmodes ovl_lowmodes;
+typedef struct ovl_net ovl_net;
+
+const char* ovl_last_error(void);
+int ovl_version(void);
+
+/* ---------------------------------------------------------------- geometry
+ * Site ordering and neighbours of the periodic lattice (Sec. II, Fig. 1).
+ * ovl_geom_create: OVL_E_DIMS if an extent is odd or < 2, or N >= 2^31.
+ * ovl_geom_neighbors_device: fills dev_table, int32 [8][N] in eo order,
+ *   table[d][eo(s)] = eo(neighbour of s), d = 0..3 for +x,+y,+z,+t and
+ *   d = 4..7 for -x..-t, computed on the GPU by the same index arithmetic
+ *   the stencil kernels use.  Caller-owned device buffer of 32*N bytes.
+ */
+int ovl_geom_create(const int32_t dims[4], ovl_geom** out);
+int ovl_geom_destroy(ovl_geom* g);
+int ovl_geom_volume(const ovl_geom* g, int64_t* n_sites);
+int ovl_geom_eo_index(const ovl_geom* g, const int32_t xyzt[4], int32_t* eo);
+int ovl_geom_neighbors_device(const ovl_geom* g, int32_t* dev_table, ovl_stream_t s);
+
+/* ----------------------------------------------------------------- spinors
+ * ovl_spinor_bytes: bytes of a batch of nrhs spinors at precision prec.
+ * ovl_pack_spinor / ovl_unpack_spinor: device-to-device conversion between
+ *   the canonical AoS complex128 layout and the library layout.  Down-
+ *   conversion rounds to nearest even; FP64 -> FP16/BF16 goes through FP32
+ *   (two such roundings).  src and dst must not overlap.
+ */
+int ovl_spinor_bytes(const ovl_geom* g, ovl_prec prec, int nrhs, size_t* bytes);
+int ovl_pack_spinor(const ovl_geom* g, const double* dev_aos, void* dev_out, ovl_prec prec,
+                    int nrhs, ovl_stream_t s);
+int ovl_unpack_spinor(const ovl_geom* g, const void* dev_in, double* dev_aos, ovl_prec prec,
+                      int nrhs, ovl_stream_t s);
+
+/* ------------------------------------------------------------------- gauge
+ * ovl_gauge_create: copies and packs the links U_mu(x) (Sec. II, Fig. 1)
+ *   from a device AoS complex128 [N][4][3][3] buffer into the FP64 18-real
+ *   representation, which every FP64 operator uses.  The source buffer may
+ *   be freed after the call returns.
+ * ovl_gauge_set_repr: (re)builds the representation that operators at
+ *   spinor precision prec (F32, F16 or BF16) use: links stored at that
+ *   precision with 18 reals, or 12 reals (rows 0 and 1; row 2 rebuilt as
+ *   conj(row0 x row1), valid for SU(3)).  compress12 = 1 checks that
+ *   every link is unitary with det 1 to 1e-12 (FP64) and returns
+ *   OVL_E_NOT_SU3 otherwise.  Also accepts prec = F64 with compress12 = 1
+ *   to switch FP64 operators to 12-real links.
+ */
+int ovl_gauge_create(const ovl_geom* g, const double* dev_aos, ovl_stream_t s, ovl_gauge** out);
+int ovl_gauge_set_repr(ovl_gauge* u, ovl_prec prec, int compress12, ovl_stream_t s);
+int ovl_gauge_destroy(ovl_gauge* u);
+const ovl_geom* ovl_gauge_geom(const ovl_gauge* u);
+
+/* --------------------------------------------------------------- operators
+ * ovl_dslash: out = D_w(m) in (eq. 1-2) for a batch of nrhs spinors:
+ *   out(x) = (4+m) in(x) - 1/2 sum_mu [ U_mu(x)(1-gamma_mu) in(x+mu)
+ *                                     + U_mu(x-mu)^dag (1+gamma_mu) in(x-mu) ].
+ *   parity = 0 or 1 writes only the even or odd sites of out (the other
+ *   half of out is left untouched); parity = 2 writes both.  in and out
+ *   use precision prec; FP64 computes in double, the others in float.
+ *   out == in gives OVL_E_ALIAS.
+ * ovl_hw_apply: out = H_w in = gamma5 D_w(-rho) in (Sec. II).
+ */
+int ovl_dslash(void* out, const void* in, const ovl_gauge* u, double m, int parity, ovl_prec prec,
+               int nrhs, ovl_stream_t s);
+int ovl_hw_apply(void* out, const void* in, const ovl_gauge* u, double rho, ovl_prec prec, int nrhs,
+                 ovl_stream_t s);
+
+/* -------------------------------------------------------------------- BLAS1
+ * Vector operations of Sec. III on batches of nrhs spinors of precision
+ * prec (a is one complex number per right-hand side, host array of 2*nrhs
+ * doubles re,im).  Reductions accumulate in FP64 in a fixed order
+ * (deterministic) and write 2*nrhs (dot) or nrhs (norm2) doubles to the
+ * host array result; they synchronise the stream.
+ *   ovl_axpy : y <- a x + y          ovl_xpay : y <- x + a y
+ *   ovl_dot  : result_r = x_r^dag y_r     ovl_norm2: result_r = ||x_r||^2
+ *   ovl_convert: dst <- src with precision change (RNE on down-conversion)
+ */
+int ovl_axpy(const ovl_geom* g, const double* a, const void* x, void* y, ovl_prec prec, int nrhs,
+             ovl_stream_t s);
+int ovl_xpay(const ovl_geom* g, const void* x, const double* a, void* y, ovl_prec prec, int nrhs,
+             ovl_stream_t s);
+int ovl_dot(const ovl_geom* g, const void* x, const void* y, ovl_prec prec, int nrhs, double* result,
+            ovl_stream_t s);
+int ovl_norm2(const ovl_geom* g, const void* x, ovl_prec prec, int nrhs, double* result,
+              ovl_stream_t s);
+int ovl_convert(const ovl_geom* g, const void* src, ovl_prec src_prec, void* dst, ovl_prec dst_prec,
+                int nrhs, ovl_stream_t s);
+
+/* ------------------------------------------------------------ sign function
+ * Polynomial approximation of sign(H_w) (eq. 4-5, Sec. V): Q = H_w/lam_max,
+ * P(x) ~ x^{-1/2} on [eps, 1] with eps = (lam_lo/lam_max)^2, expanded in
+ * Chebyshev polynomials T_k(y), y = (2x - 1 - eps)/(1 - eps), and evaluated
+ * on vectors by the Clenshaw recursion (2n+1 applications of D_w).
+ * The coefficients are the Chebyshev interpolant of x^{-1/2} at the n+1
+ * Chebyshev-Gauss nodes (c_0 halved).
+ * ovl_sign_create: lam_max must bound |spectrum(H_w)| from above and lam_lo
+ *   bound |lambda| from below on the subspace the polynomial acts on (with
+ *   low modes: |lambda_l|).  n > 0 fixes the order; n = 0 picks the
+ *   smallest n whose measured delta = max |1 - sqrt(x) P(x)| (400000 points
+ *   of [eps,1]) is <= delta.  OVL_E_ARG unless 0 < lam_lo < lam_max.
+ * ovl_sign_info: order n, eps and the measured delta.
+ * ovl_sign_coeffs: copies c_0..c_n (n+1 doubles; cap = buffer length).
+ */
+int ovl_sign_create(double lam_lo, double lam_max, double delta, int n, ovl_sign** out);
+int ovl_sign_destroy(ovl_sign* s);
+int ovl_sign_info(const ovl_sign* s, int* n, double* eps, double* delta_measured);
+int ovl_sign_coeffs(const ovl_sign* s, double* c, int cap);
+
+/* ---------------------------------------------------------------- low modes
+ * The l eigenpairs (lambda_i, eta_i) of H_w closest to zero (eq. 6-7).
+ * ovl_lowmodes_create: V is a caller-owned device buffer of ell FP64 spinors
+ *   (library layout, back to back), orthonormal; lambda is a host array of
+ *   ell eigenvalues of H_w (copied).  The handle BORROWS V: it must stay
+ *   valid and unchanged for the handle's lifetime.
+ * ovl_lowmodes_project: psi_h = in - sum_i (eta_i^dag in) eta_i and
+ *   w = sum_i sign(lambda_i) (eta_i^dag in) eta_i for a batch of nrhs <= 12
+ *   spinors at precision prec; the inner products accumulate in FP64.
+ */
+int ovl_lowmodes_create(const ovl_geom* g, int ell, const void* V, const double* lambda, ovl_lowmodes** out);
+int ovl_lowmodes_destroy(ovl_lowmodes* lm);
+int ovl_lowmodes_project(const ovl_lowmodes* lm, const void* in, void* psi_h, void* w, ovl_prec prec, int nrhs,
+                         ovl_stream_t s);
+
+/* ----------------------------------------------------------------- overlap
+ * ovl_sign_apply: out = sign(H_w) in ~ sum_i sign(lambda_i)(eta_i^dag in) eta_i
+ *   + Q P(Q^2) in_h (eq. 7); lowmodes may be NULL (no projection).
+ * ovl_overlap_apply: out = D(m) in with D(m) = rho D + m (1 - D/2) and
+ *   D = 1 + gamma5 sign(H_w) (eq. 3, 8), i.e.
+ *   D(m) in = (rho + m/2) in + (rho - m/2) gamma5 sign(H_w) in;
+ *   dagger = 1 gives D(m)^dag in = (rho + m/2) in + (rho - m/2) sign(H_w) gamma5 in.
+ *   H_w = gamma5 D_w(-rho).  Batches of nrhs <= 12 with low modes.
+ *   Precision prec applies to in, out, the links and the Clenshaw iterates.
+ *   out must not alias in or the eigenvectors (OVL_E_ALIAS).
+ */
+int ovl_sign_apply(void* out, const void* in, const ovl_gauge* u, double rho, const ovl_sign* sign,
+                   const ovl_lowmodes* lowmodes, ovl_prec prec, int nrhs, ovl_stream_t s);
+int ovl_overlap_apply(void* out, const void* in, const ovl_gauge* u, double rho, double m, const ovl_sign* sign,
+                      const ovl_lowmodes* lowmodes, int dagger, ovl_prec prec, int nrhs, ovl_stream_t s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OVL_H */

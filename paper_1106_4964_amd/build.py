@@ -1,0 +1,87 @@
+"""Builds libovl.so (HIP, gfx950) in-tree with hipcc.
+
+    python -m paper_1106_4964_amd.build        # or build() from Python
+
+Every translation unit under csrc/ is compiled to an object with hipcc and
+linked into paper_1106_4964_amd/libovl.so.  Objects go to _build/ and are
+rebuilt when their source, csrc/*.h or include/ovl.h is newer.
+"""
+from __future__ import annotations
+
+import glob
+import os
+import subprocess
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+BUILD = os.path.join(ROOT, "_build")
+LIB = os.path.join(HERE, "libovl.so")
+ARCH = os.environ.get("OVL_ARCH", "gfx950")
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+CXXFLAGS = [
+    "-O3",
+    "-std=c++17",
+    "--offload-arch=" + ARCH,
+    "-fPIC",
+    "-Wall",
+    "-Wno-unused-function",
+    "-Wno-unused-variable",
+    # no packed-FP32 instructions anywhere in device code
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-I" + INCLUDE,
+    "-I" + CSRC,
+]
+LDFLAGS = ["-shared", "--offload-arch=" + ARCH, "-lrocblas"]
+
+
+def _sources():
+    return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+
+
+def _headers():
+    return glob.glob(os.path.join(CSRC, "*.h")) + [os.path.join(INCLUDE, "ovl.h")]
+
+
+def _obj(src):
+    return os.path.join(BUILD, os.path.basename(src) + ".o")
+
+
+def _compile(src, force):
+    obj = _obj(src)
+    newest = max(os.path.getmtime(p) for p in [src] + _headers())
+    if not force and os.path.exists(obj) and os.path.getmtime(obj) >= newest:
+        return obj, None
+    cmd = [HIPCC] + CXXFLAGS + ["-c", src, "-o", obj]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        return obj, "$ " + " ".join(cmd) + "\n" + r.stdout + r.stderr
+    return obj, None
+
+
+def build(force: bool = True, jobs: int = 8) -> str:
+    """Compile every HIP source and link libovl.so; returns its path."""
+    os.makedirs(BUILD, exist_ok=True)
+    srcs = _sources()
+    with ThreadPoolExecutor(max_workers=min(jobs, len(srcs))) as ex:
+        results = list(ex.map(lambda s: _compile(s, force), srcs))
+    errors = [e for _, e in results if e]
+    if errors:
+        raise RuntimeError("hipcc failed:\n" + "\n".join(errors))
+    objs = [o for o, _ in results]
+    tmp = LIB + ".tmp"
+    cmd = [HIPCC] + LDFLAGS + objs + ["-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("link failed:\n$ " + " ".join(cmd) + "\n" + r.stdout + r.stderr)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    force = "--incremental" not in sys.argv
+    print(build(force=force))

@@ -1,0 +1,271 @@
+// Vector operations and reductions (arXiv:1106.4964 Sec. III: the local
+// vector operations and the scalar product / norm that the solvers use).
+//
+// Every kernel walks a vector as 16-byte blocks, so one thread moves one
+// fully coalesced 16-byte load per operand whatever the storage precision.
+// Reductions accumulate in FP64: each block of a fixed-size grid reduces its
+// grid-stride share with wave64 shuffles and LDS, and a second one-block
+// kernel adds the per-block partials in a fixed order, so a given input
+// always gives the same bits.
+#include "ops.h"
+
+namespace ovl {
+namespace {
+
+constexpr int RED_BLOCKS = 1024;
+constexpr int RED_THREADS = 256;
+
+template <int P>
+__global__ void axpy_kernel(size_t n16, const double* a, const char* x, char* y, size_t vstride) {
+  using real = typename Prec<P>::real;
+  constexpr int cpb = Prec<P>::cpb;
+  const size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x;
+  if (i >= n16) return;
+  const size_t off = blockIdx.y * vstride + i * 16;
+  const Cx<real> ar = {static_cast<real>(a[2 * blockIdx.y]), static_cast<real>(a[2 * blockIdx.y + 1])};
+  Cx<real> xv[cpb], yv[cpb];
+  Block<P>::load(x + off, xv);
+  Block<P>::load(y + off, yv);
+#pragma unroll
+  for (int k = 0; k < cpb; ++k) yv[k] = yv[k] + ar * xv[k];
+  Block<P>::store(y + off, yv);
+}
+
+template <int P>
+__global__ void xpay_kernel(size_t n16, const char* x, const double* a, char* y, size_t vstride) {
+  using real = typename Prec<P>::real;
+  constexpr int cpb = Prec<P>::cpb;
+  const size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x;
+  if (i >= n16) return;
+  const size_t off = blockIdx.y * vstride + i * 16;
+  const Cx<real> ar = {static_cast<real>(a[2 * blockIdx.y]), static_cast<real>(a[2 * blockIdx.y + 1])};
+  Cx<real> xv[cpb], yv[cpb];
+  Block<P>::load(x + off, xv);
+  Block<P>::load(y + off, yv);
+#pragma unroll
+  for (int k = 0; k < cpb; ++k) yv[k] = xv[k] + ar * yv[k];
+  Block<P>::store(y + off, yv);
+}
+
+// Precision conversion, one thread per site (the block layouts differ
+// between precisions, so whole spinors are moved).
+template <int PS, int PD>
+__global__ void convert_kernel(int Nh, const char* src, char* dst, size_t sstride, size_t dstride) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 2 * Nh) return;
+  const int p = e >= Nh, h = e - p * Nh;
+  using rs = typename Prec<PS>::real;
+  using rd = typename Prec<PD>::real;
+  Cx<rs> a[12];
+  SpinorIO<PS>::load(src + blockIdx.y * sstride, p, h, Nh, a);
+  Cx<rd> b[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) b[k] = {static_cast<rd>(a[k].re), static_cast<rd>(a[k].im)};
+  SpinorIO<PD>::store(dst + blockIdx.y * dstride, p, h, Nh, b);
+}
+
+// out = gamma5 in: complex index c = 3*spin + colour, spins 2 and 3 negated.
+template <int P>
+__global__ void gamma5_kernel(size_t n16, int Nh, const char* x, char* y, size_t vstride) {
+  using real = typename Prec<P>::real;
+  constexpr int cpb = Prec<P>::cpb;
+  const size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x;
+  if (i >= n16) return;
+  const size_t off = blockIdx.y * vstride + i * 16;
+  const int j = static_cast<int>((i / Nh) % (12 / cpb));  // block index within the site
+  Cx<real> v[cpb];
+  Block<P>::load(x + off, v);
+#pragma unroll
+  for (int k = 0; k < cpb; ++k)
+    if (j * cpb + k >= 6) v[k] = real(-1) * v[k];
+  Block<P>::store(y + off, v);
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Block sum of (re, im) pairs; result valid in thread 0.
+__device__ inline void block_sum2(double& re, double& im) {
+  __shared__ double sre[RED_THREADS / 64], sim[RED_THREADS / 64];
+  re = wave_sum(re);
+  im = wave_sum(im);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) {
+    sre[w] = re;
+    sim[w] = im;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    re = 0.0;
+    im = 0.0;
+    for (int k = 0; k < RED_THREADS / 64; ++k) {
+      re += sre[k];
+      im += sim[k];
+    }
+  }
+}
+
+template <int P, bool NORM>
+__global__ __launch_bounds__(RED_THREADS) void dot_partial_kernel(size_t n16, const char* x, const char* y,
+                                                                  size_t vstride, double* partial) {
+  using real = typename Prec<P>::real;
+  constexpr int cpb = Prec<P>::cpb;
+  double re = 0.0, im = 0.0;
+  const char* xb = x + blockIdx.y * vstride;
+  const char* yb = NORM ? xb : y + blockIdx.y * vstride;
+  for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < n16;
+       i += static_cast<size_t>(gridDim.x) * blockDim.x) {
+    Cx<real> xv[cpb];
+    Block<P>::load(xb + i * 16, xv);
+    if constexpr (NORM) {
+#pragma unroll
+      for (int k = 0; k < cpb; ++k) {
+        re += static_cast<double>(xv[k].re) * xv[k].re;
+        re += static_cast<double>(xv[k].im) * xv[k].im;
+      }
+    } else {
+      Cx<real> yv[cpb];
+      Block<P>::load(yb + i * 16, yv);
+#pragma unroll
+      for (int k = 0; k < cpb; ++k) {
+        const double xr = xv[k].re, xi = xv[k].im, yr = yv[k].re, yi = yv[k].im;
+        re += xr * yr + xi * yi;
+        im += xr * yi - xi * yr;
+      }
+    }
+  }
+  block_sum2(re, im);
+  if (threadIdx.x == 0) {
+    double* o = partial + (static_cast<size_t>(blockIdx.y) * gridDim.x + blockIdx.x) * 2;
+    o[0] = re;
+    o[1] = im;
+  }
+}
+
+// One block per rhs: fixed-order sum of the RED_BLOCKS partials.
+__global__ __launch_bounds__(RED_THREADS) void dot_final_kernel(const double* partial, int nparts, double* out) {
+  double re = 0.0, im = 0.0;
+  const double* p = partial + static_cast<size_t>(blockIdx.x) * nparts * 2;
+  for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
+    re += p[2 * i];
+    im += p[2 * i + 1];
+  }
+  block_sum2(re, im);
+  if (threadIdx.x == 0) {
+    out[2 * blockIdx.x] = re;
+    out[2 * blockIdx.x + 1] = im;
+  }
+}
+
+template <template <int> class K, typename... Args>
+void dispatch_prec(int prec, Args&&... args) {
+  switch (prec) {
+    case OVL_F64: K<OVL_F64>::run(args...); break;
+    case OVL_F32: K<OVL_F32>::run(args...); break;
+    case OVL_F16: K<OVL_F16>::run(args...); break;
+    case OVL_BF16: K<OVL_BF16>::run(args...); break;
+    default: throw Error(OVL_E_PRECISION, "unknown precision");
+  }
+}
+
+template <int P>
+struct AxpyL {
+  static void run(size_t n16, const double* a, const void* x, void* y, int nrhs, size_t vs, hipStream_t s) {
+    dim3 grid((n16 + 255) / 256, nrhs);
+    hipLaunchKernelGGL(axpy_kernel<P>, grid, dim3(256), 0, s, n16, a, static_cast<const char*>(x),
+                       static_cast<char*>(y), vs);
+  }
+};
+template <int P>
+struct XpayL {
+  static void run(size_t n16, const void* x, const double* a, void* y, int nrhs, size_t vs, hipStream_t s) {
+    dim3 grid((n16 + 255) / 256, nrhs);
+    hipLaunchKernelGGL(xpay_kernel<P>, grid, dim3(256), 0, s, n16, static_cast<const char*>(x), a,
+                       static_cast<char*>(y), vs);
+  }
+};
+template <int P>
+struct G5L {
+  static void run(size_t n16, int Nh, const void* x, void* y, int nrhs, size_t vs, hipStream_t s) {
+    dim3 grid((n16 + 255) / 256, nrhs);
+    hipLaunchKernelGGL(gamma5_kernel<P>, grid, dim3(256), 0, s, n16, Nh, static_cast<const char*>(x),
+                       static_cast<char*>(y), vs);
+  }
+};
+template <int P>
+struct DotL {
+  static void run(size_t n16, const void* x, const void* y, int nrhs, size_t vs, double* out, hipStream_t s) {
+    WsBuf part(static_cast<size_t>(nrhs) * RED_BLOCKS * 2 * sizeof(double), s);
+    double* pp = static_cast<double*>(part.p);
+    if (y)
+      hipLaunchKernelGGL((dot_partial_kernel<P, false>), dim3(RED_BLOCKS, nrhs), dim3(RED_THREADS), 0, s, n16,
+                         static_cast<const char*>(x), static_cast<const char*>(y), vs, pp);
+    else
+      hipLaunchKernelGGL((dot_partial_kernel<P, true>), dim3(RED_BLOCKS, nrhs), dim3(RED_THREADS), 0, s, n16,
+                         static_cast<const char*>(x), nullptr, vs, pp);
+    hipLaunchKernelGGL(dot_final_kernel, dim3(nrhs), dim3(RED_THREADS), 0, s, pp, RED_BLOCKS, out);
+  }
+};
+
+template <int PS>
+struct ConvL {
+  template <int PD>
+  static void go(int Nh, const void* src, void* dst, int nrhs, hipStream_t s) {
+    const size_t ss = static_cast<size_t>(2) * Nh * spinor_bytes_per_site(PS);
+    const size_t ds = static_cast<size_t>(2) * Nh * spinor_bytes_per_site(PD);
+    dim3 grid((2 * Nh + 255) / 256, nrhs);
+    hipLaunchKernelGGL((convert_kernel<PS, PD>), grid, dim3(256), 0, s, Nh, static_cast<const char*>(src),
+                       static_cast<char*>(dst), ss, ds);
+  }
+  static void run(int dprec, int Nh, const void* src, void* dst, int nrhs, hipStream_t s) {
+    switch (dprec) {
+      case OVL_F64: go<OVL_F64>(Nh, src, dst, nrhs, s); break;
+      case OVL_F32: go<OVL_F32>(Nh, src, dst, nrhs, s); break;
+      case OVL_F16: go<OVL_F16>(Nh, src, dst, nrhs, s); break;
+      case OVL_BF16: go<OVL_BF16>(Nh, src, dst, nrhs, s); break;
+      default: throw Error(OVL_E_PRECISION, "unknown precision");
+    }
+  }
+};
+
+}  // namespace
+
+void blas_axpy(int prec, size_t n16, const double* a, const void* x, void* y, int nrhs, size_t vstride,
+               hipStream_t s) {
+  dispatch_prec<AxpyL>(prec, n16, a, x, y, nrhs, vstride, s);
+  OVL_HIP(hipGetLastError());
+}
+
+void blas_xpay(int prec, size_t n16, const void* x, const double* a, void* y, int nrhs, size_t vstride,
+               hipStream_t s) {
+  dispatch_prec<XpayL>(prec, n16, x, a, y, nrhs, vstride, s);
+  OVL_HIP(hipGetLastError());
+}
+
+void blas_gamma5(int prec, size_t vstride, const void* x, void* y, int nrhs, hipStream_t s) {
+  const size_t n16 = vstride / 16;
+  const int Nh = static_cast<int>(n16 / (2 * spinor_blocks(prec)));
+  dispatch_prec<G5L>(prec, n16, Nh, x, y, nrhs, vstride, s);
+  OVL_HIP(hipGetLastError());
+}
+
+void blas_dot(int prec, size_t n16, const void* x, const void* y, int nrhs, size_t vstride, double* dev_out,
+              hipStream_t s) {
+  dispatch_prec<DotL>(prec, n16, x, y, nrhs, vstride, dev_out, s);
+  OVL_HIP(hipGetLastError());
+}
+
+void blas_norm2(int prec, size_t n16, const void* x, int nrhs, size_t vstride, double* dev_out, hipStream_t s) {
+  dispatch_prec<DotL>(prec, n16, x, static_cast<const void*>(nullptr), nrhs, vstride, dev_out, s);
+  OVL_HIP(hipGetLastError());
+}
+
+void blas_convert(int sprec, const void* src, int dprec, void* dst, size_t nsites, int nrhs, hipStream_t s) {
+  dispatch_prec<ConvL>(sprec, dprec, static_cast<int>(nsites / 2), src, dst, nrhs, s);
+  OVL_HIP(hipGetLastError());
+}
+
+}  // namespace ovl

@@ -1,0 +1,450 @@
+// Internal declarations shared by the libovl translation units.
+//
+// Device-side: complex arithmetic, the 16-byte-block spinor layout for each
+// storage precision, the gauge-link layouts (18 or 12 reals), the lattice
+// index arithmetic, and the launch helpers.  Host-side: handle structs,
+// error reporting and the workspace pool.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "ovl.h"
+
+namespace ovl {
+
+// ---------------------------------------------------------------- errors
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+void set_last_error(const std::string& msg);
+
+#define OVL_HIP(call)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      throw ::ovl::Error(OVL_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define OVL_REQUIRE(cond, code, msg)                  \
+  do {                                                \
+    if (!(cond)) throw ::ovl::Error((code), (msg)); \
+  } while (0)
+
+// Runs f() and converts exceptions into ABI status codes.
+template <class F>
+int guard(F&& f) {
+  try {
+    return f();
+  } catch (const Error& e) {
+    set_last_error(e.what());
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_last_error("host allocation failed");
+    return OVL_E_NOMEM;
+  } catch (const std::exception& e) {
+    set_last_error(e.what());
+    return OVL_E_ARG;
+  }
+}
+
+// -------------------------------------------------------------- complex
+template <typename T>
+struct Cx {
+  T re, im;
+};
+
+template <typename T>
+__host__ __device__ inline Cx<T> cx(T r, T i) {
+  return Cx<T>{r, i};
+}
+template <typename T>
+__host__ __device__ inline Cx<T> operator+(Cx<T> a, Cx<T> b) {
+  return {a.re + b.re, a.im + b.im};
+}
+template <typename T>
+__host__ __device__ inline Cx<T> operator-(Cx<T> a, Cx<T> b) {
+  return {a.re - b.re, a.im - b.im};
+}
+template <typename T>
+__host__ __device__ inline Cx<T> operator*(Cx<T> a, Cx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T>
+__host__ __device__ inline Cx<T> operator*(T s, Cx<T> a) {
+  return {s * a.re, s * a.im};
+}
+template <typename T>
+__host__ __device__ inline Cx<T> conj(Cx<T> a) {
+  return {a.re, -a.im};
+}
+// conj(a) * b
+template <typename T>
+__host__ __device__ inline Cx<T> cmul_conj(Cx<T> a, Cx<T> b) {
+  return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+// i*a and -i*a
+template <typename T>
+__host__ __device__ inline Cx<T> times_i(Cx<T> a) {
+  return {-a.im, a.re};
+}
+template <typename T>
+__host__ __device__ inline Cx<T> times_mi(Cx<T> a) {
+  return {a.im, -a.re};
+}
+
+// ------------------------------------------------------ storage formats
+// A storage format maps 12 complex numbers of compute type `real` to
+// 16-byte blocks (spinors) or to K elements of E bytes (links).
+struct bf16_t {
+  uint16_t bits;
+};
+
+__host__ __device__ inline float bf16_to_float(uint16_t b) {
+  uint32_t u = static_cast<uint32_t>(b) << 16;
+  float f;
+  memcpy(&f, &u, 4);
+  return f;
+}
+// Round to nearest even; NaN stays a (quiet) NaN.
+__host__ __device__ inline uint16_t float_to_bf16(float f) {
+  uint32_t u;
+  memcpy(&u, &f, 4);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return static_cast<uint16_t>((u >> 16) | 0x40);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return static_cast<uint16_t>(u >> 16);
+}
+
+template <int P>
+struct Prec;  // P = ovl_prec value
+
+template <>
+struct Prec<OVL_F64> {
+  using real = double;
+  static constexpr int cpb = 1;  // complex per 16-byte block
+};
+template <>
+struct Prec<OVL_F32> {
+  using real = float;
+  static constexpr int cpb = 2;
+};
+template <>
+struct Prec<OVL_F16> {
+  using real = float;
+  static constexpr int cpb = 4;
+};
+template <>
+struct Prec<OVL_BF16> {
+  using real = float;
+  static constexpr int cpb = 4;
+};
+
+constexpr int spinor_blocks(int prec) { return prec == OVL_F64 ? 12 : (prec == OVL_F32 ? 6 : 3); }
+inline size_t spinor_bytes_per_site(int prec) { return 16u * spinor_blocks(prec); }
+
+// Load/store one 16-byte block as `cpb` complex numbers of compute type.
+template <int P>
+struct Block;
+
+template <>
+struct Block<OVL_F64> {
+  __device__ static inline void load(const void* p, Cx<double>* c) {
+    double2 v = *reinterpret_cast<const double2*>(p);
+    c[0] = {v.x, v.y};
+  }
+  __device__ static inline void store(void* p, const Cx<double>* c) {
+    *reinterpret_cast<double2*>(p) = make_double2(c[0].re, c[0].im);
+  }
+};
+template <>
+struct Block<OVL_F32> {
+  __device__ static inline void load(const void* p, Cx<float>* c) {
+    float4 v = *reinterpret_cast<const float4*>(p);
+    c[0] = {v.x, v.y};
+    c[1] = {v.z, v.w};
+  }
+  __device__ static inline void store(void* p, const Cx<float>* c) {
+    *reinterpret_cast<float4*>(p) = make_float4(c[0].re, c[0].im, c[1].re, c[1].im);
+  }
+};
+typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
+template <>
+struct Block<OVL_F16> {
+  __device__ static inline void load(const void* p, Cx<float>* c) {
+    half8_t v = *reinterpret_cast<const half8_t*>(p);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) c[k] = {static_cast<float>(v[2 * k]), static_cast<float>(v[2 * k + 1])};
+  }
+  __device__ static inline void store(void* p, const Cx<float>* c) {
+    half8_t v;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      v[2 * k] = static_cast<_Float16>(c[k].re);
+      v[2 * k + 1] = static_cast<_Float16>(c[k].im);
+    }
+    *reinterpret_cast<half8_t*>(p) = v;
+  }
+};
+template <>
+struct Block<OVL_BF16> {
+  __device__ static inline void load(const void* p, Cx<float>* c) {
+    uint4 v = *reinterpret_cast<const uint4*>(p);
+    uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      c[k] = {bf16_to_float(static_cast<uint16_t>(w[k] & 0xffffu)),
+              bf16_to_float(static_cast<uint16_t>(w[k] >> 16))};
+  }
+  __device__ static inline void store(void* p, const Cx<float>* c) {
+    uint32_t w[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      w[k] = static_cast<uint32_t>(float_to_bf16(c[k].re)) |
+             (static_cast<uint32_t>(float_to_bf16(c[k].im)) << 16);
+    *reinterpret_cast<uint4*>(p) = make_uint4(w[0], w[1], w[2], w[3]);
+  }
+};
+
+// One spinor (12 complex) of a field in the [parity][block][Nh] layout.
+// `base` points at the start of the vector, `h` is the half-lattice index,
+// `p` the parity.
+template <int P>
+struct SpinorIO {
+  using real = typename Prec<P>::real;
+  static constexpr int cpb = Prec<P>::cpb;
+  static constexpr int nb = 12 / cpb;
+  __device__ static inline void load(const void* base, int p, int h, int Nh, Cx<real>* s) {
+    const char* b = static_cast<const char*>(base) + (static_cast<size_t>(p) * nb * Nh + h) * 16;
+#pragma unroll
+    for (int j = 0; j < nb; ++j) Block<P>::load(b + static_cast<size_t>(j) * Nh * 16, s + j * cpb);
+  }
+  __device__ static inline void store(void* base, int p, int h, int Nh, const Cx<real>* s) {
+    char* b = static_cast<char*>(base) + (static_cast<size_t>(p) * nb * Nh + h) * 16;
+#pragma unroll
+    for (int j = 0; j < nb; ++j) Block<P>::store(b + static_cast<size_t>(j) * Nh * 16, s + j * cpb);
+  }
+};
+
+// ------------------------------------------------------------ link formats
+// Layout [mu][parity][K][Nh] of E-byte elements.  R = 18 or 12 reals.
+//   F64: E = 16 (one complex);            K = 9 or 6
+//   F32: R=18 -> E = 8 (one complex),     K = 9;  R=12 -> E = 16 (two), K = 3
+//   F16/BF16: R=18 -> E = 4 (one complex), K = 9; R=12 -> E = 8 (two), K = 3
+template <int P, int R>
+struct LinkFmt {
+  static constexpr int ncx = R / 2;  // stored complex numbers
+  static constexpr int cpe = (P == OVL_F64 || R == 18) ? 1 : 2;  // complex per element
+  static constexpr int K = ncx / cpe;
+  static constexpr int E = (P == OVL_F64 ? 16 : (P == OVL_F32 ? 8 : 4)) * cpe;
+};
+
+template <int P>
+struct ScalarIO;
+template <>
+struct ScalarIO<OVL_F64> {
+  __device__ static inline Cx<double> load1(const char* p) {
+    double2 v = *reinterpret_cast<const double2*>(p);
+    return {v.x, v.y};
+  }
+  __device__ static inline void load2(const char* p, Cx<double>* c) {
+    c[0] = load1(p);
+    c[1] = load1(p + 16);
+  }
+  __device__ static inline void store1(char* p, Cx<double> c) {
+    *reinterpret_cast<double2*>(p) = make_double2(c.re, c.im);
+  }
+};
+template <>
+struct ScalarIO<OVL_F32> {
+  __device__ static inline Cx<float> load1(const char* p) {
+    float2 v = *reinterpret_cast<const float2*>(p);
+    return {v.x, v.y};
+  }
+  __device__ static inline void load2(const char* p, Cx<float>* c) {
+    float4 v = *reinterpret_cast<const float4*>(p);
+    c[0] = {v.x, v.y};
+    c[1] = {v.z, v.w};
+  }
+  __device__ static inline void store1(char* p, Cx<float> c) {
+    *reinterpret_cast<float2*>(p) = make_float2(c.re, c.im);
+  }
+  __device__ static inline void store2(char* p, const Cx<float>* c) {
+    *reinterpret_cast<float4*>(p) = make_float4(c[0].re, c[0].im, c[1].re, c[1].im);
+  }
+};
+typedef _Float16 half2v_t __attribute__((ext_vector_type(2)));
+typedef _Float16 half4v_t __attribute__((ext_vector_type(4)));
+template <>
+struct ScalarIO<OVL_F16> {
+  __device__ static inline Cx<float> load1(const char* p) {
+    half2v_t v = *reinterpret_cast<const half2v_t*>(p);
+    return {static_cast<float>(v[0]), static_cast<float>(v[1])};
+  }
+  __device__ static inline void load2(const char* p, Cx<float>* c) {
+    half4v_t v = *reinterpret_cast<const half4v_t*>(p);
+    c[0] = {static_cast<float>(v[0]), static_cast<float>(v[1])};
+    c[1] = {static_cast<float>(v[2]), static_cast<float>(v[3])};
+  }
+  __device__ static inline void store1(char* p, Cx<float> c) {
+    half2v_t v;
+    v[0] = static_cast<_Float16>(c.re);
+    v[1] = static_cast<_Float16>(c.im);
+    *reinterpret_cast<half2v_t*>(p) = v;
+  }
+  __device__ static inline void store2(char* p, const Cx<float>* c) {
+    half4v_t v;
+    v[0] = static_cast<_Float16>(c[0].re);
+    v[1] = static_cast<_Float16>(c[0].im);
+    v[2] = static_cast<_Float16>(c[1].re);
+    v[3] = static_cast<_Float16>(c[1].im);
+    *reinterpret_cast<half4v_t*>(p) = v;
+  }
+};
+template <>
+struct ScalarIO<OVL_BF16> {
+  __device__ static inline Cx<float> load1(const char* p) {
+    uint32_t w = *reinterpret_cast<const uint32_t*>(p);
+    return {bf16_to_float(static_cast<uint16_t>(w & 0xffffu)), bf16_to_float(static_cast<uint16_t>(w >> 16))};
+  }
+  __device__ static inline void load2(const char* p, Cx<float>* c) {
+    uint2 w = *reinterpret_cast<const uint2*>(p);
+    c[0] = {bf16_to_float(static_cast<uint16_t>(w.x & 0xffffu)), bf16_to_float(static_cast<uint16_t>(w.x >> 16))};
+    c[1] = {bf16_to_float(static_cast<uint16_t>(w.y & 0xffffu)), bf16_to_float(static_cast<uint16_t>(w.y >> 16))};
+  }
+  __device__ static inline void store1(char* p, Cx<float> c) {
+    *reinterpret_cast<uint32_t*>(p) =
+        static_cast<uint32_t>(float_to_bf16(c.re)) | (static_cast<uint32_t>(float_to_bf16(c.im)) << 16);
+  }
+  __device__ static inline void store2(char* p, const Cx<float>* c) {
+    uint2 w;
+    w.x = static_cast<uint32_t>(float_to_bf16(c[0].re)) | (static_cast<uint32_t>(float_to_bf16(c[0].im)) << 16);
+    w.y = static_cast<uint32_t>(float_to_bf16(c[1].re)) | (static_cast<uint32_t>(float_to_bf16(c[1].im)) << 16);
+    *reinterpret_cast<uint2*>(p) = w;
+  }
+};
+
+// Loads the 3x3 link matrix u[row][col] of direction mu at (p, h).
+template <int P, int R>
+struct LinkIO {
+  using F = LinkFmt<P, R>;
+  using real = typename Prec<P>::real;
+  __device__ static inline void load(const void* links, int mu, int p, int h, int Nh, Cx<real> (*u)[3]) {
+    const char* b = static_cast<const char*>(links) +
+                    ((static_cast<size_t>(mu) * 2 + p) * F::K * Nh + h) * F::E;
+    Cx<real> c[9];
+    if constexpr (F::cpe == 1) {
+#pragma unroll
+      for (int k = 0; k < F::ncx; ++k) c[k] = ScalarIO<P>::load1(b + static_cast<size_t>(k) * Nh * F::E);
+    } else {
+#pragma unroll
+      for (int k = 0; k < F::K; ++k) ScalarIO<P>::load2(b + static_cast<size_t>(k) * Nh * F::E, c + 2 * k);
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) u[k / 3][k % 3] = c[k];
+    if constexpr (R == 18) {
+#pragma unroll
+      for (int k = 6; k < 9; ++k) u[2][k - 6] = c[k];
+    } else {
+      // row2 = conj(row0 x row1)
+      u[2][0] = conj(u[0][1] * u[1][2] - u[0][2] * u[1][1]);
+      u[2][1] = conj(u[0][2] * u[1][0] - u[0][0] * u[1][2]);
+      u[2][2] = conj(u[0][0] * u[1][1] - u[0][1] * u[1][0]);
+    }
+  }
+};
+
+// ------------------------------------------------------------ geometry
+struct Geo {
+  int Lx, Ly, Lz, Lt;
+  int lxh;       // Lx / 2
+  int Nh;        // N / 2
+  int sy, sz, st;  // half-index strides of y, z, t
+};
+
+// Coordinates of half-index h at parity p.
+__host__ __device__ inline void site_coords(const Geo& g, int p, int h, int& x, int& y, int& z, int& t) {
+  int xh = h % g.lxh;
+  int r = h / g.lxh;
+  y = r % g.Ly;
+  r /= g.Ly;
+  z = r % g.Lz;
+  t = r / g.Lz;
+  x = 2 * xh + ((p + y + z + t) & 1);
+}
+
+// Half-index of the 8 neighbours (all of parity 1-p), order +x,+y,+z,+t,-x,-y,-z,-t.
+__host__ __device__ inline void site_neighbors(const Geo& g, int h, int x, int y, int z, int t, int* nb) {
+  const int base = h - (x >> 1);  // h with the x part removed
+  int xp = (x + 1 == g.Lx) ? 0 : x + 1;
+  int xm = (x == 0) ? g.Lx - 1 : x - 1;
+  nb[0] = base + (xp >> 1);
+  nb[4] = base + (xm >> 1);
+  nb[1] = h + ((y + 1 == g.Ly) ? -(g.Ly - 1) * g.sy : g.sy);
+  nb[5] = h + ((y == 0) ? (g.Ly - 1) * g.sy : -g.sy);
+  nb[2] = h + ((z + 1 == g.Lz) ? -(g.Lz - 1) * g.sz : g.sz);
+  nb[6] = h + ((z == 0) ? (g.Lz - 1) * g.sz : -g.sz);
+  nb[3] = h + ((t + 1 == g.Lt) ? -(g.Lt - 1) * g.st : g.st);
+  nb[7] = h + ((t == 0) ? (g.Lt - 1) * g.st : -g.st);
+}
+
+// XCD-aware block remap: hardware hands workgroups to the 8 XCDs round
+// robin; this makes each XCD take one contiguous range of logical blocks so
+// that neighbouring sites share an L2.
+__device__ inline int xcd_remap(int b, int nblocks) {
+  constexpr int NX = 8;
+  int q = nblocks / NX, r = nblocks % NX;
+  int x = b % NX, j = b / NX;
+  return x * q + (x < r ? x : r) + j;
+}
+
+// ------------------------------------------------------------- handles
+}  // namespace ovl
+
+struct ovl_geom {
+  int dims[4];
+  int64_t N;
+  ovl::Geo geo;
+};
+
+struct ovl_gauge {
+  ovl_geom geom;             // the handle keeps its own copy of the geometry
+  void* master = nullptr;    // FP64, 18 reals: source of every representation
+  void* links[4] = {nullptr, nullptr, nullptr, nullptr};  // used per spinor precision
+  int recon[4] = {0, 0, 0, 0};                             // 18 or 12 (0 = absent)
+};
+
+namespace ovl {
+
+// Device workspace pool.  A buffer released on stream s is only handed out
+// again for work on the same stream, so stream order makes reuse safe even
+// while earlier kernels that used it are still running.
+void* ws_get(size_t bytes, hipStream_t s);
+void ws_put(void* p, hipStream_t s);
+
+struct WsBuf {
+  void* p = nullptr;
+  hipStream_t s;
+  WsBuf(size_t bytes, hipStream_t st) : p(ws_get(bytes, st)), s(st) {}
+  ~WsBuf() { ws_put(p, s); }
+  WsBuf(const WsBuf&) = delete;
+  WsBuf& operator=(const WsBuf&) = delete;
+};
+
+inline size_t spinor_vec_bytes(const ovl_geom* g, int prec) {
+  return static_cast<size_t>(g->N) * spinor_bytes_per_site(prec);
+}
+
+void check_prec(int prec);
+void check_nrhs(int nrhs);
+
+}  // namespace ovl

@@ -1,0 +1,59 @@
+// Internal host-side entry points of libovl (called by the C ABI in abi.hip
+// and by the higher-level drivers: sign function, solvers, eigensolver).
+#pragma once
+
+#include "core.h"
+
+namespace ovl {
+
+// ---------------------------------------------------------------- stencil
+// out = G( a*in + b*hop(in) ) + sum_j cv[j] * G_j(v[j])
+//   hop(in)(x) = sum_mu [ U_mu(x)(1-gamma_mu) in(x+mu) + U_mu(x-mu)^dag (1+gamma_mu) in(x-mu) ]
+//   G = gamma5 if g5 else 1;  G_j = gamma5 if bit j of g5v else 1.
+// Output sites: parities [par0, par0 + npar).  A batch of nrhs vectors is
+// vstride bytes apart (inputs, outputs and the extra vectors alike).
+struct StencilArgs {
+  Geo g;
+  void* out;
+  const void* in;
+  const void* links;
+  const void* v[3];
+  double cv[3];
+  int nv;
+  int g5v;
+  double a, b;
+  int g5;
+  int par0, npar;
+  size_t vstride;
+};
+
+void launch_stencil(const StencilArgs& A, int prec, int recon, int nrhs, hipStream_t s);
+
+// Representation of the links that operators at spinor precision prec use.
+const void* gauge_links(const ovl_gauge* u, int prec, int* recon);
+
+// ------------------------------------------------------------------ BLAS1
+// Vectors of `n16` 16-byte blocks each (a whole batch can be passed as one
+// vector).  Scalars in device memory are FP64 complex (re, im).
+void blas_axpy(int prec, size_t n16, const double* a, const void* x, void* y, int nrhs, size_t vstride,
+               hipStream_t s);
+void blas_xpay(int prec, size_t n16, const void* x, const double* a, void* y, int nrhs, size_t vstride,
+               hipStream_t s);
+// y = gamma5 x for a batch of nrhs vectors of vstride bytes each.
+void blas_gamma5(int prec, size_t vstride, const void* x, void* y, int nrhs, hipStream_t s);
+void blas_convert(int sprec, const void* src, int dprec, void* dst, size_t nsites, int nrhs, hipStream_t s);
+// Deterministic two-stage reductions; results (re, im) per rhs written to
+// device memory dev_out[2*rhs].
+void blas_dot(int prec, size_t n16, const void* x, const void* y, int nrhs, size_t vstride, double* dev_out,
+              hipStream_t s);
+void blas_norm2(int prec, size_t n16, const void* x, int nrhs, size_t vstride, double* dev_out,
+                hipStream_t s);
+
+// ------------------------------------------------------------ sign / overlap
+void lowmode_project(const ovl_lowmodes* lm, const void* psi, void* psih, void* w, int prec, int nrhs, int g5w,
+                     hipStream_t s);
+// mode 0: sign(H_w) in;  1: D(m) in;  2: D(m)^dag in
+void overlap_apply(void* out, const void* in, const ovl_gauge* u, double rho, double m, const ovl_sign* sg,
+                   const ovl_lowmodes* lm, int mode, int prec, int nrhs, hipStream_t s);
+
+}  // namespace ovl

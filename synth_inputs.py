@@ -29,6 +29,7 @@ __all__ = [
     "gaussian_spinor",
     "point_source",
     "point_sources",
+    "orthonormal_spinors",
 ]
 
 
@@ -112,3 +113,12 @@ def point_source(dims, spin: int, colour: int, site=(0, 0, 0, 0)) -> np.ndarray:
 def point_sources(dims, site=(0, 0, 0, 0)) -> np.ndarray:
     """The 12 spin x colour point sources, shape [12,N,4,3]; index = 3*spin+colour."""
     return np.stack([point_source(dims, s, c, site) for s in range(4) for c in range(3)])
+
+
+def orthonormal_spinors(dims, count: int, seed: int) -> np.ndarray:
+    """`count` random orthonormal spinor fields, shape [count,N,4,3] (QR of Gaussians)."""
+    n = volume(dims)
+    rng = np.random.default_rng(seed)
+    g = rng.standard_normal((n * 12, count)) + 1j * rng.standard_normal((n * 12, count))
+    q, _ = np.linalg.qr(g)
+    return np.ascontiguousarray(q.T.reshape(count, n, 4, 3))

@@ -1,0 +1,72 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every symbol the
+header declares, and rejects bad arguments before touching the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ovl.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ovl_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1106_4964_amd import ovl
+
+    names = declared_symbols()
+    assert len(names) > 15
+    missing = [n for n in names if not hasattr(ovl.lib, n)]
+    assert not missing, missing
+    # and the binding wraps each of them under the same name
+    assert not [n for n in names if not hasattr(ovl, n)]
+
+
+def test_geometry_errors_and_indices():
+    from paper_1106_4964_amd import ovl
+
+    for bad in [(3, 4, 4, 4), (4, 4, 4, 0), (4, 1, 4, 4)]:
+        with pytest.raises(ovl.OvlError) as e:
+            ovl.Geometry(bad)
+        assert e.value.name == "OVL_E_DIMS"
+    g = ovl.Geometry((4, 4, 4, 4))
+    assert g.N == 256
+    assert g.eo_index((1, 0, 0, 0)) == 128
+    assert g.eo_index((3, 3, 3, 3)) == 127
+    assert g.eo_index((1, 2, 3, 1)) == 188
+    with pytest.raises(ovl.OvlError):
+        g.eo_index((4, 0, 0, 0))
+
+
+def test_spinor_bytes():
+    from paper_1106_4964_amd import ovl
+
+    g = ovl.Geometry((4, 4, 4, 6))
+    assert g.spinor_bytes(ovl.OVL_F64) == 384 * 192
+    assert g.spinor_bytes(ovl.OVL_F32, 12) == 12 * 384 * 96
+    assert g.spinor_bytes(ovl.OVL_F16) == 384 * 48
+    assert g.spinor_bytes(ovl.OVL_BF16) == 384 * 48
+    with pytest.raises(ovl.OvlError):
+        g.spinor_bytes(7)
+    with pytest.raises(ovl.OvlError):
+        g.spinor_bytes(ovl.OVL_F64, 0)
+
+
+def test_null_and_alias_arguments_rejected_without_gpu():
+    from paper_1106_4964_amd import ovl
+
+    g = ovl.Geometry((4, 4, 4, 4))
+    with pytest.raises(ovl.OvlError) as e:
+        ovl.ovl_dslash(None, None, None, 0.0, 2, ovl.OVL_F64, 1, 0)
+    assert e.value.name == "OVL_E_ARG"
+    with pytest.raises(ovl.OvlError) as e:
+        ovl.ovl_pack_spinor(g, 0x1000, 0x1000, ovl.OVL_F64, 1, 0)
+    assert e.value.name == "OVL_E_ALIAS"
+    with pytest.raises(ovl.OvlError) as e:
+        ovl.ovl_convert(g, 0x1000, ovl.OVL_F64, 0x1000, ovl.OVL_F32, 1, 0)
+    assert e.value.name == "OVL_E_ALIAS"

@@ -1,0 +1,132 @@
+"""GPU parity of geometry, packing and the Wilson stencil against the oracle."""
+import numpy as np
+import pytest
+
+import synth_inputs as si
+from oracle import dirac
+from oracle.lattice import Lattice
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+from paper_1106_4964_amd import ovl  # noqa: E402
+
+import gpu_util as gu  # noqa: E402
+
+SIZES = [(4, 4, 4, 4), (6, 6, 6, 8), (8, 6, 4, 10), (2, 2, 2, 2)]
+PRECS = [ovl.OVL_F64, ovl.OVL_F32, ovl.OVL_F16, ovl.OVL_BF16]
+
+
+@pytest.mark.parametrize("dims", SIZES)
+def test_neighbor_table_bit_exact(dims):
+    lat = Lattice(dims)
+    g = ovl.Geometry(dims)
+    dev = torch.empty((8, g.N), dtype=torch.int32, device=gu.DEV)
+    ovl.ovl_geom_neighbors_device(g, dev, None)
+    torch.cuda.synchronize()
+    assert np.array_equal(dev.cpu().numpy(), lat.neighbor_table())
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_pack_roundtrip(prec):
+    dims = (6, 6, 6, 8)
+    g = ovl.Geometry(dims)
+    psi = np.stack([si.gaussian_spinor(dims, 5 + r) for r in range(3)])
+    back = gu.unpack(g, gu.pack(g, psi, prec, 3), prec, 3)
+    if prec == ovl.OVL_F64:
+        assert np.array_equal(back, psi)
+    else:
+        assert gu.max_rel_err(back, psi) <= 2 * gu.UNIT_ROUNDOFF[prec] * np.max(np.abs(psi)) / np.max(np.abs(psi))
+        # the even-odd reorder itself is exact: F32 equals a numpy float32 rounding
+        if prec == ovl.OVL_F32:
+            r = psi.real.astype(np.float32).astype(np.float64) + 1j * psi.imag.astype(np.float32).astype(np.float64)
+            assert np.array_equal(back, r)
+
+
+def _dslash_case(dims, prec, compress12, m, parity, seed=1, nrhs=1):
+    lat = Lattice(dims)
+    U = si.gauge_field(dims, 0.3, seed)
+    psi = np.stack([si.gaussian_spinor(dims, 100 + seed + r) for r in range(nrhs)])
+    g = ovl.Geometry(dims)
+    reprs = [] if (prec == ovl.OVL_F64 and not compress12) else [(prec, compress12)]
+    gauge = gu.make_gauge(g, U, reprs)
+    inp = gu.pack(g, psi, prec, nrhs)
+    out = gu.pack(g, np.zeros_like(psi), prec, nrhs)
+    ovl.ovl_dslash(out, inp, gauge, m, parity, prec, nrhs, None)
+    got = gu.unpack(g, out, prec, nrhs)
+    if nrhs == 1:
+        got = got[None]
+    if parity == 2:
+        want = np.stack([dirac.wilson_dslash(lat, U, p, m) for p in psi])
+    else:
+        want = np.stack([dirac.wilson_dslash_parity(lat, U, p, m, parity) for p in psi])
+    return got, want
+
+
+@pytest.mark.parametrize("dims", SIZES)
+@pytest.mark.parametrize("m", [-1.5, 0.0, 0.1])
+def test_dslash_f64_parity(dims, m):
+    got, want = _dslash_case(dims, ovl.OVL_F64, 0, m, 2)
+    assert gu.max_rel_err(got, want) < 1e-13
+
+
+@pytest.mark.parametrize("parity", [0, 1])
+def test_dslash_single_parity_leaves_other_half(parity):
+    got, want = _dslash_case((6, 6, 6, 8), ovl.OVL_F64, 0, 0.1, parity)
+    # the untouched half of `out` still holds the zeros it was packed with
+    assert gu.max_rel_err(got, want) < 1e-13
+
+
+def test_dslash_f64_compressed_links():
+    got, want = _dslash_case((8, 6, 4, 10), ovl.OVL_F64, 1, -1.5, 2)
+    assert gu.max_rel_err(got, want) < 1e-13
+
+
+@pytest.mark.parametrize("prec", [ovl.OVL_F32, ovl.OVL_F16, ovl.OVL_BF16])
+@pytest.mark.parametrize("compress12", [0, 1])
+def test_dslash_low_precision_error(prec, compress12):
+    got, want = _dslash_case((8, 6, 4, 10), prec, compress12, -1.5, 2)
+    # storage rounding of input, links and output; FP32 arithmetic
+    tol = 16 * gu.UNIT_ROUNDOFF[prec] + 4e-7
+    err = gu.rel_err(got, want)
+    print("prec", prec, "c12", compress12, "rel err", err)
+    assert err < tol
+
+
+def test_dslash_batch_equals_single():
+    dims = (6, 6, 6, 8)
+    got, want = _dslash_case(dims, ovl.OVL_F64, 0, 0.1, 2, nrhs=3)
+    assert gu.max_rel_err(got, want) < 1e-13
+
+
+def test_hw_apply_gamma5_hermitian():
+    dims = (8, 6, 4, 10)
+    lat = Lattice(dims)
+    U = si.gauge_field(dims, 0.25, 3)
+    psi = si.gaussian_spinor(dims, 7)
+    g = ovl.Geometry(dims)
+    gauge = gu.make_gauge(g, U)
+    inp = gu.pack(g, psi, ovl.OVL_F64)
+    out = gu.empty_field(g, ovl.OVL_F64)
+    ovl.ovl_hw_apply(out, inp, gauge, 1.5, ovl.OVL_F64, 1, None)
+    got = gu.unpack(g, out, ovl.OVL_F64)
+    assert gu.max_rel_err(got, dirac.hw_apply(lat, U, psi, 1.5)) < 1e-13
+
+
+def test_not_su3_rejected():
+    dims = (4, 4, 4, 4)
+    U = si.gauge_field(dims, 0.3, 1)
+    U[5, 2] *= 1.01
+    g = ovl.Geometry(dims)
+    gauge = gu.make_gauge(g, U)
+    with pytest.raises(ovl.OvlError) as e:
+        gauge.set_repr(ovl.OVL_F16, 1)
+    assert e.value.name == "OVL_E_NOT_SU3"
+    gauge.set_repr(ovl.OVL_F16, 0)  # 18 reals need no SU(3) structure
+
+
+def test_dslash_full_size_24x64():
+    """The 24^3 x 64 lattice: GPU FP64 stencil against the oracle on every site."""
+    dims = (24, 24, 24, 64)
+    got, want = _dslash_case(dims, ovl.OVL_F64, 0, -1.5, 2, seed=5)
+    assert gu.max_rel_err(got, want) < 1e-13

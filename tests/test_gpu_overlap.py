@@ -1,0 +1,137 @@
+"""GPU parity of the projection, the polynomial sign and the overlap operator."""
+import numpy as np
+import pytest
+
+import synth_inputs as si
+from oracle import dense, dirac, sign
+from oracle.lattice import Lattice
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+from paper_1106_4964_amd import ovl  # noqa: E402
+
+import gpu_util as gu  # noqa: E402
+
+RHO = 1.5
+
+
+def _lowmodes_dev(g, V):
+    dev = gu.pack(g, V.reshape(len(V), g.N, 4, 3), ovl.OVL_F64, len(V))
+    return dev
+
+
+@pytest.fixture(scope="module")
+def c1():
+    """4^4, c = 0.3, seeds 1/101, exact spectral bounds from the dense H_w."""
+    dims = (4, 4, 4, 4)
+    lat = Lattice(dims)
+    U = si.gauge_field(dims, 0.3, 1)
+    H = dense.dense_hw(lat, U, RHO)
+    w = np.linalg.eigvalsh(H)
+    return dict(dims=dims, lat=lat, U=U, lo=float(np.min(np.abs(w))), hi=float(np.max(np.abs(w))),
+                psi=si.gaussian_spinor(dims, 101))
+
+
+def test_sign_c1_degree200_f64(c1):
+    """4^4 config: polynomial of degree 200, no projection, FP64 to 1e-12."""
+    g = ovl.Geometry(c1["dims"])
+    gauge = gu.make_gauge(g, c1["U"])
+    s_lib = ovl.Sign(c1["lo"], c1["hi"], n=200)
+    s_or = sign.make_sign(c1["lo"], c1["hi"], 200)
+    inp = gu.pack(g, c1["psi"], ovl.OVL_F64)
+    out = gu.empty_field(g, ovl.OVL_F64)
+    ovl.ovl_sign_apply(out, inp, gauge, RHO, s_lib, None, ovl.OVL_F64, 1, None)
+    got = gu.unpack(g, out, ovl.OVL_F64)
+    want = sign.sign_apply(c1["lat"], c1["U"], c1["psi"], RHO, s_or)
+    assert gu.max_rel_err(got, want) < 1e-12
+
+
+@pytest.mark.parametrize("dagger", [0, 1])
+@pytest.mark.parametrize("m", [0.01, 0.05])
+def test_overlap_c1_f64(c1, dagger, m):
+    g = ovl.Geometry(c1["dims"])
+    gauge = gu.make_gauge(g, c1["U"])
+    s_lib = ovl.Sign(c1["lo"], c1["hi"], n=200)
+    s_or = sign.make_sign(c1["lo"], c1["hi"], 200)
+    inp = gu.pack(g, c1["psi"], ovl.OVL_F64)
+    out = gu.empty_field(g, ovl.OVL_F64)
+    ovl.ovl_overlap_apply(out, inp, gauge, RHO, m, s_lib, None, dagger, ovl.OVL_F64, 1, None)
+    got = gu.unpack(g, out, ovl.OVL_F64)
+    want = sign.overlap_apply(c1["lat"], c1["U"], c1["psi"], RHO, m, s_or, dagger=bool(dagger))
+    assert gu.max_rel_err(got, want) < 1e-12
+
+
+@pytest.mark.parametrize("nrhs", [1, 3, 12])
+def test_projection_parity(nrhs):
+    dims = (6, 6, 6, 8)
+    g = ovl.Geometry(dims)
+    ell = 21
+    V = si.orthonormal_spinors(dims, ell, seed=7)
+    lam = np.linspace(-0.9, 0.8, ell)
+    lm = ovl.LowModes(g, _lowmodes_dev(g, V), lam)
+    psi = np.stack([si.gaussian_spinor(dims, 30 + r) for r in range(nrhs)])
+    inp = gu.pack(g, psi, ovl.OVL_F64, nrhs)
+    ph = gu.empty_field(g, ovl.OVL_F64, nrhs)
+    w = gu.empty_field(g, ovl.OVL_F64, nrhs)
+    ovl.ovl_lowmodes_project(lm, inp, ph, w, ovl.OVL_F64, nrhs, None)
+    got_h = gu.unpack(g, ph, ovl.OVL_F64, nrhs).reshape(nrhs, g.N, 4, 3)
+    got_w = gu.unpack(g, w, ovl.OVL_F64, nrhs).reshape(nrhs, g.N, 4, 3)
+    for r in range(nrhs):
+        c, want_h = sign.project_low(V, psi[r])
+        want_w = ((np.sign(lam) * c) @ V.reshape(ell, -1)).reshape(g.N, 4, 3)
+        assert gu.max_rel_err(got_h[r], want_h) < 1e-13
+        assert gu.max_rel_err(got_w[r], want_w) < 1e-13
+
+
+@pytest.mark.parametrize("dagger", [0, 1])
+def test_overlap_with_lowmodes_f64_ragged(dagger):
+    """6x6x6x8 (ragged tiles), synthetic orthonormal 'low modes', 12 RHS."""
+    dims = (6, 6, 6, 8)
+    lat = Lattice(dims)
+    g = ovl.Geometry(dims)
+    U = si.gauge_field(dims, 0.25, 2)
+    gauge = gu.make_gauge(g, U)
+    ell = 9
+    V = si.orthonormal_spinors(dims, ell, seed=3)
+    lam = np.array([0.3, -0.31, 0.35, -0.4, 0.41, 0.45, -0.5, 0.52, -0.55])
+    lm = ovl.LowModes(g, _lowmodes_dev(g, V), lam)
+    s_lib = ovl.Sign(0.55, 6.6, n=40)
+    s_or = sign.make_sign(0.55, 6.6, 40)
+    nrhs = 12
+    psi = np.stack([si.gaussian_spinor(dims, 50 + r) for r in range(nrhs)])
+    inp = gu.pack(g, psi, ovl.OVL_F64, nrhs)
+    out = gu.empty_field(g, ovl.OVL_F64, nrhs)
+    ovl.ovl_overlap_apply(out, inp, gauge, RHO, 0.01, s_lib, lm, dagger, ovl.OVL_F64, nrhs, None)
+    got = gu.unpack(g, out, ovl.OVL_F64, nrhs)
+    for r in (0, 5, 11):
+        want = sign.overlap_apply(lat, U, psi[r], RHO, 0.01, s_or, V, lam, dagger=bool(dagger))
+        assert gu.max_rel_err(got[r], want) < 1e-12
+
+
+@pytest.mark.parametrize("prec", [ovl.OVL_F32, ovl.OVL_F16, ovl.OVL_BF16])
+def test_overlap_low_precision_error(c1, prec):
+    """Error of the low-precision overlap apply against the FP64 oracle (stated)."""
+    g = ovl.Geometry(c1["dims"])
+    gauge = gu.make_gauge(g, c1["U"], [(prec, 1)])
+    n = 120
+    s_lib = ovl.Sign(c1["lo"], c1["hi"], n=n)
+    s_or = sign.make_sign(c1["lo"], c1["hi"], n)
+    inp = gu.pack(g, c1["psi"], prec)
+    out = gu.empty_field(g, prec)
+    ovl.ovl_overlap_apply(out, inp, gauge, RHO, 0.01, s_lib, None, 0, prec, 1, None)
+    got = gu.unpack(g, out, prec)
+    want = sign.overlap_apply(c1["lat"], c1["U"], c1["psi"], RHO, 0.01, s_or)
+    err = gu.rel_err(got, want)
+    print("overlap apply prec %d rel err %.3e" % (prec, err))
+    bound = {ovl.OVL_F32: 1e-5, ovl.OVL_F16: 3e-2, ovl.OVL_BF16: 2e-1}[prec]
+    assert err < bound
+
+
+def test_overlap_aliasing_rejected(c1):
+    g = ovl.Geometry(c1["dims"])
+    gauge = gu.make_gauge(g, c1["U"])
+    s_lib = ovl.Sign(c1["lo"], c1["hi"], n=10)
+    buf = gu.pack(g, c1["psi"], ovl.OVL_F64)
+    with pytest.raises(ovl.OvlError) as e:
+        ovl.ovl_overlap_apply(buf, buf, gauge, RHO, 0.01, s_lib, None, 0, ovl.OVL_F64, 1, None)
+    assert e.value.name == "OVL_E_ALIAS"
