@@ -1,0 +1,309 @@
+"""Benchmark of the overlap-operator hot path on one MI355X.
+
+Workload (default): 24^3 x 64 periodic lattice, links U = exp(i 0.25 H)
+(seeded, synthetic), rho = 1.5, the 100 H_w eigenvectors closest to zero
+projected, polynomial sign to delta = 1e-10, 12 spin x colour point sources
+at the origin, quark masses 0.01 and 0.05, FP16 link and spinor storage with
+FP32 arithmetic (FP64 projection inner products and reductions).
+
+A timed step is the operator work of one CG iteration on the 12 sources:
+one batched D(m) apply and one batched D(m)^dag apply (each: projection,
+2n+1 stencil launches of the Clenshaw recursion, combine).  `value` is
+overlap applies per second (each rhs counts once).  Also reported:
+  dslash      - GB/s of the stencil (model bytes / HIP-event time) per
+                precision and batch size, and the roofline of the dominant
+                kernel (the FP16 12-real 12-rhs stencil);
+  cg          - time to an FP64 true residual of 1e-10 for the mixed-
+                precision 12-rhs solve (HIP-graph iterations) and for the
+                plain FP64 solve, and their ratio;
+  cpu_baseline- the FP64 numpy oracle on the host, on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cg]
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import math
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "dslash GB/s + D_ov applies/s at 24^3x64; CG time to 1e-10 vs plain FP64"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--dims", type=str, default="24,24,24,64")
+    ap.add_argument("--ell", type=int, default=100)
+    ap.add_argument("--delta", type=float, default=1e-10)
+    ap.add_argument("--prec", type=str, default="f16")
+    ap.add_argument("--no-cg", action="store_true")
+    ap.add_argument("--fp64-cg-rhs", type=int, default=12, help="rhs of the plain FP64 CG comparison")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-only", action="store_true", help=argparse.SUPPRESS)
+    return ap.parse_args()
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline: the oracle, timed in a child process limited to one thread
+# ---------------------------------------------------------------------------
+def cpu_baseline_child(dims, n, ell):
+    import numpy as np
+
+    import synth_inputs as si
+    from oracle import dirac, sign
+    from oracle.lattice import Lattice
+
+    lat = Lattice(dims)
+    U = si.gauge_field(dims, 0.25, 3)
+    psi = si.gaussian_spinor(dims, 103)
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        dirac.hw_apply(lat, U, psi, 1.5)
+    t_dw = (time.perf_counter() - t0) / reps
+    # projection on ell vectors: time it on 4 vectors and scale linearly
+    V = np.stack([si.gaussian_spinor(dims, 200 + i) for i in range(4)])
+    t0 = time.perf_counter()
+    sign.project_low(V, psi)
+    t_proj4 = time.perf_counter() - t0
+    t_apply = t_dw * (2 * n + 1) + t_proj4 * ell / 4.0
+    print(json.dumps({"t_dw": t_dw, "t_proj4": t_proj4, "t_apply": t_apply, "reps": reps}))
+
+
+def cpu_baseline(dims, n, ell):
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    env["HIP_VISIBLE_DEVICES"] = ""
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-only", "--dims", ",".join(map(str, dims)),
+           "--ell", str(ell), "--delta", str(n)]
+    r = subprocess.run(cmd, capture_output=True, text=True, env=env, timeout=600)
+    if r.returncode != 0:
+        raise RuntimeError("cpu baseline failed: " + r.stderr[-2000:])
+    d = json.loads(r.stdout.strip().splitlines()[-1])
+    return {
+        "value": 1.0 / d["t_apply"],
+        "unit": "D_ov applies/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": ("FP64 numpy oracle, one thread: %d H_w applications at %s (%.2f s each) and the "
+                   "projection on 4 vectors (%.2f s), extrapolated to one overlap apply of 2n+1 = %d "
+                   "stencil applications and %d projected vectors"
+                   % (d["reps"], "x".join(map(str, dims)), d["t_dw"], d["t_proj4"], 2 * n + 1, ell)),
+    }
+
+
+# ---------------------------------------------------------------------------
+def main():
+    args = parse()
+    dims = tuple(int(v) for v in args.dims.split(","))
+    if args.cpu_only:
+        cpu_baseline_child(dims, int(args.delta), args.ell)
+        return
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the whole lattice lives in one MI355X's HBM and this build "
+              "has no multi-GPU path (--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth_inputs as si
+    from paper_1106_4964_amd import ovl
+
+    dev = torch.device("cuda:0")
+    rho, masses = 1.5, (0.01, 0.05)
+    prec = ovl.PREC[args.prec]
+    R = 12
+    t_setup = time.perf_counter()
+
+    log("gauge field %s" % (dims,))
+    g = ovl.Geometry(dims)
+    U = si.gauge_field(dims, 0.25, 3)
+    gauge = ovl.Gauge(g, torch.from_numpy(U).to(dev))
+    del U
+    gauge.set_repr(prec, 1)
+    gauge.set_repr(ovl.OVL_F32, 1)
+
+    def pack(a, p, n):
+        out = torch.empty(g.spinor_bytes(p, n), dtype=torch.uint8, device=dev)
+        ovl.ovl_pack_spinor(g, torch.from_numpy(np.ascontiguousarray(a)).to(dev), out, p, n, None)
+        return out
+
+    log("Lanczos bound")
+    v0 = pack(si.gaussian_spinor(dims, 17), ovl.OVL_F64, 1)
+    lam = ctypes.c_double()
+    ovl.ovl_hw_bound(gauge, rho, v0, 60, ctypes.byref(lam), None, None, None)
+    lam_max = lam.value * (1 + 1e-6)
+    del v0
+
+    ell = args.ell
+    m = ell + max(12, ell // 4)
+    log("eigensolver: %d of %d vectors" % (ell, m))
+    V = torch.empty(g.spinor_bytes(ovl.OVL_F64, m), dtype=torch.uint8, device=dev)
+    for i in range(0, m, 8):
+        k = min(8, m - i)
+        blk = np.stack([si.gaussian_spinor(dims, 1000 + i + j) for j in range(k)])
+        ovl.ovl_pack_spinor(g, torch.from_numpy(blk).to(dev),
+                            V[i * g.spinor_bytes(ovl.OVL_F64):], ovl.OVL_F64, k, None)
+    lams = np.zeros(ell)
+    est = ovl.EigStats()
+    rc = ovl.ovl_hw_eigs(gauge, rho, ell, m, V, lams, lam_max, 1e-12, 60, 40, ctypes.byref(est), None)
+    log("eigensolver rc %d: %d passes, %d H_w applies, max residual %.2e, %.1f s, |lambda_l| = %.4f"
+        % (rc, est.iterations, est.hw_applies, est.max_residual, est.seconds, abs(lams[-1])))
+    Vk = V[: ell * g.spinor_bytes(ovl.OVL_F64)]
+    lm = ovl.LowModes(g, Vk, lams)
+    sgn = ovl.Sign(abs(lams[-1]), lam_max, delta=args.delta)
+    log("sign: n = %d, sqrt(eps) = %.4f, delta = %.2e" % (sgn.n, math.sqrt(sgn.eps), sgn.delta))
+
+    b64 = pack(si.point_sources(dims), ovl.OVL_F64, R)
+    bP = torch.empty(g.spinor_bytes(prec, R), dtype=torch.uint8, device=dev)
+    ovl.ovl_convert(g, b64, ovl.OVL_F64, bP, prec, R, None)
+    y1 = torch.empty_like(bP)
+    y2 = torch.empty_like(bP)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t_setup
+    log("setup %.1f s" % t_setup)
+
+    # ---------------------------------------------------------------- steps
+    def step():
+        ovl.ovl_overlap_apply(y1, bP, gauge, rho, masses[0], sgn, lm, 0, prec, R, None)
+        ovl.ovl_overlap_apply(y2, y1, gauge, rho, masses[0], sgn, lm, 1, prec, R, None)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t_steps = time.perf_counter() - t0
+    ms_per_step = 1e3 * t_steps / args.steps
+    applies_per_s = 2 * R * args.steps / t_steps
+    log("step %.2f ms -> %.1f D_ov applies/s" % (ms_per_step, applies_per_s))
+
+    # ------------------------------------------------------------- dslash
+    N = g.N
+    reals_per_link = 12
+
+    def stencil_time(p, nrhs, reps=20):
+        x = torch.empty(g.spinor_bytes(p, nrhs), dtype=torch.uint8, device=dev)
+        ovl.ovl_convert(g, b64[: g.spinor_bytes(ovl.OVL_F64, nrhs)], ovl.OVL_F64, x, p, nrhs, None)
+        y = torch.empty_like(x)
+        ovl.ovl_hw_apply(y, x, gauge, rho, p, nrhs, None)
+        s = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            ovl.ovl_hw_apply(y, x, gauge, rho, p, nrhs, None)
+        e1.record(s)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e-3  # seconds per launch
+
+    bytes_per_real = {ovl.OVL_F64: 8, ovl.OVL_F32: 4, ovl.OVL_F16: 2, ovl.OVL_BF16: 2}
+
+    def model_bytes(p, L, nrhs):
+        # compulsory traffic, full lattice, one pass: links once per launch,
+        # each input and output spinor once
+        return N * bytes_per_real[p] * (4 * L + 48 * nrhs)
+
+    dslash = {}
+    gauge.set_repr(ovl.OVL_F64, 0)
+    for name, p, L, nrhs in [("f64_18_1rhs", ovl.OVL_F64, 18, 1), ("f32_12_1rhs", ovl.OVL_F32, 12, 1),
+                             ("f16_12_1rhs", prec, 12, 1), ("f16_12_12rhs", prec, 12, 12)]:
+        t = stencil_time(p, nrhs)
+        gbs = model_bytes(p, L, nrhs) / t / 1e9
+        dslash[name] = {"us": round(t * 1e6, 2), "model_GBps": round(gbs, 1),
+                        "gflops": round(1368.0 * N * nrhs / t / 1e9, 1)}
+        log("dslash %s: %.1f us, %.0f GB/s (model bytes)" % (name, t * 1e6, gbs))
+    dom = dslash["f16_12_12rhs"]
+    dom_bytes = model_bytes(prec, 12, 12)
+    roofline = {
+        "bound": "hbm",
+        "achieved": dom["model_GBps"],
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(dom["model_GBps"] / HBM_PEAK_GBS, 4),
+        "traffic": None,
+        "kernel": "stencil_kernel<F16, 12-real links, 0 extra vectors>, 12 rhs, 24^3x64",
+        "bytes_per_launch": dom_bytes,
+        "avg_launch_us": dom["us"],
+    }
+
+    # ----------------------------------------------------------------- CG
+    cg = None
+    if not args.no_cg:
+        cg = {}
+
+        def solve(p, nrhs, m, graph, inner_tol):
+            x = torch.zeros(g.spinor_bytes(ovl.OVL_F64, nrhs), dtype=torch.uint8, device=dev)
+            opts = ovl.SolveOpts(p, inner_tol, graph, 1, 60)
+            st = ovl.SolveStats()
+            rc = ovl.ovl_cg_solve(x, b64[: g.spinor_bytes(ovl.OVL_F64, nrhs)], nrhs, gauge, rho, m, sgn, lm,
+                                  1e-10, 20000, opts, st, None)
+            res = max(st.true_residual[r] for r in range(nrhs))
+            return {"rc": rc, "seconds": round(st.seconds, 3), "iterations": st.iterations,
+                    "restarts": st.restarts, "max_true_residual": res, "sign_applies": st.sign_applies}
+
+        for m in masses:
+            r_mixed = solve(prec, R, m, 8, 1e-3)
+            log("CG mixed m=%.2f: %s" % (m, r_mixed))
+            cg["mixed_f16_12rhs_m%.2f" % m] = r_mixed
+        nfp = max(1, min(R, args.fp64_cg_rhs))
+        r64 = solve(ovl.OVL_F64, nfp, masses[0], 0, 0.0)
+        log("CG plain FP64 m=%.2f (%d rhs): %s" % (masses[0], nfp, r64))
+        cg["plain_f64_m%.2f_%drhs" % (masses[0], nfp)] = r64
+        t64 = r64["seconds"] * (R / nfp)
+        cg["speedup_vs_plain_f64_m%.2f" % masses[0]] = round(t64 / cg["mixed_f16_12rhs_m%.2f" % masses[0]]["seconds"], 2)
+        if nfp < R:
+            cg["note"] = "plain FP64 time scaled from %d to 12 rhs" % nfp
+
+    cpu = None
+    if not args.no_cpu:
+        log("cpu baseline (oracle)")
+        cpu = cpu_baseline(dims, sgn.n, ell)
+
+    out = {
+        "metric": METRIC,
+        "value": round(applies_per_s, 3),
+        "unit": "D_ov applies/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "overlap D(m) and D(m)^dag on 12 point sources, %s lattice, %s storage / f32 compute, "
+                        "%d projected H_w modes, polynomial sign delta=%g (n=%d), m=%g"
+                        % ("x".join(map(str, dims)), args.prec, ell, args.delta, sgn.n, masses[0]),
+            "lattice": list(dims), "nrhs": R, "ell": ell, "sign_order": sgn.n,
+            "sqrt_eps": round(math.sqrt(sgn.eps), 5), "lam_max": round(lam_max, 5), "rho": rho,
+            "storage": args.prec, "links": "12-real", "setup_seconds": round(t_setup, 1),
+        },
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "dslash": dslash,
+        "cg": cg,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -209,6 +209,92 @@ int ovl_sign_apply(void* out, const void* in, const ovl_gauge* u, double rho, co
 int ovl_overlap_apply(void* out, const void* in, const ovl_gauge* u, double rho, double m, const ovl_sign* sign,
                       const ovl_lowmodes* lowmodes, int dagger, ovl_prec prec, int nrhs, ovl_stream_t s);
 
+/* ------------------------------------------------------------------ solvers
+ * ovl_cg_solve: solves D(m) x = b for nrhs <= 12 FP64 right-hand sides
+ *   (library layout, batch) by CG on D(m) D(m)^dag with x = D(m)^dag y, so
+ *   the iterated residual is b - D(m) x.  x holds the starting guess on
+ *   entry (zero it for a fresh solve; a saved x resumes a solve) and the
+ *   solution on exit.  An FP64 outer loop recomputes r = b - D(m) x with the
+ *   FP64 operator and restarts the inner solve on r until every rhs has
+ *   ||r|| <= tol ||b|| (defect correction).  The inner solve runs at
+ *   opts->inner_prec (FP64 = plain FP64 CG; F32/F16/BF16 need the matching
+ *   link representation) and accumulates its correction in FP64.  Krylov
+ *   scalars stay on the device; with opts->graph_chunk > 0 that many inner
+ *   iterations are captured once in a HIP graph and replayed.  A rhs that
+ *   converges is frozen (its scalars become zero) while the others go on.
+ *   Returns OVL_OK, OVL_W_NOT_CONVERGED (maxiter inner iterations or
+ *   max_restarts cycles reached; stats valid), OVL_E_BREAKDOWN or OVL_E_NAN.
+ *   opts may be NULL (plain FP64, no graph).  Work is done on a private
+ *   stream ordered after, and before, the caller's stream s.
+ * ovl_propagator: out = (1 - D/2) x (Sec. II), the propagator from a
+ *   solution x of D(m) x = b.
+ */
+typedef struct {
+  ovl_prec inner_prec; /* precision of the inner CG                       */
+  double inner_tol;    /* low-precision inner solve: relative reduction   */
+  int graph_chunk;     /* > 0: inner iterations per captured HIP graph     */
+  int check_every;     /* without graphs: iterations between host checks  */
+  int max_restarts;    /* FP64 defect-correction cycles                   */
+} ovl_solve_opts;
+
+typedef struct {
+  int iterations;                       /* inner CG iterations, all cycles   */
+  int restarts;                         /* inner solves started              */
+  double true_residual[OVL_MAX_RHS];    /* ||b - D(m)x|| / ||b|| in FP64     */
+  double seconds;                       /* wall time of the call             */
+  int64_t sign_applies;                 /* vector applications of sign(H_w)  */
+  int64_t dslash_applies;               /* vector applications of D_w        */
+  int fallback_used;                    /* FGCR only: CG finished the solve  */
+} ovl_solve_stats;
+
+int ovl_cg_solve(void* x, const void* b, int nrhs, const ovl_gauge* u, double rho, double m, const ovl_sign* sign,
+                 const ovl_lowmodes* lowmodes, double tol, int maxiter, const ovl_solve_opts* opts,
+                 ovl_solve_stats* stats, ovl_stream_t s);
+int ovl_propagator(void* out, const void* x, const ovl_gauge* u, double rho, const ovl_sign* sign,
+                   const ovl_lowmodes* lowmodes, ovl_prec prec, int nrhs, ovl_stream_t s);
+
+/* ------------------------------------------------------- spectral set-up
+ * ovl_hw_bound: FP64 Lanczos on H_w = gamma5 D_w(-rho) from the start vector
+ *   v0 (device FP64 spinor, caller-drawn), full re-orthogonalisation, `steps`
+ *   steps.  lam_max = max over the two extreme Ritz pairs of
+ *   |theta| + ||H_w y - theta y||: the normalisation ||H_w|| of Q = H_w/||H_w||
+ *   (eq. 5).  theta_min/theta_max (may be NULL): the extreme Ritz values.
+ * ovl_hw_eigs: the ell eigenpairs of H_w with smallest |lambda|, for the
+ *   projection of eq. 6-7.  Thick-restart Lanczos (FP64, full
+ *   re-orthogonalisation) on the Chebyshev polynomial T_degree of H_w^2
+ *   that damps |lambda| in [0.15 lam_max, lam_max] (Sec. V's acceleration),
+ *   then Rayleigh-Ritz with H_w on the top Ritz vectors.  V: caller-owned
+ *   device buffer of m >= ell + max(8, ell/10) FP64 spinors; on entry V[:,0]
+ *   is the start vector (e.g. Gaussian), on exit the first ell vectors are
+ *   orthonormal eigenvectors ordered by (|lambda|, lambda) and lambda[0..ell)
+ *   their eigenvalues.  Stops when every wanted pair has
+ *   ||H_w v - lambda v|| <= tol * lam_max, or after max_iter restart cycles
+ *   (OVL_W_NOT_CONVERGED).  lam_max must bound |spectrum(H_w)|.  Device
+ *   workspace: K + 5 FP64 spinors, K = max(2 want, want + 40) <= 512.
+ */
+typedef struct {
+  int iterations;      /* restart cycles                              */
+  int64_t hw_applies;  /* vector applications of H_w                  */
+  double max_residual; /* max over wanted pairs of ||H_w v - lambda v|| */
+  double seconds;
+} ovl_eig_stats;
+
+int ovl_hw_bound(const ovl_gauge* u, double rho, const void* v0, int steps, double* lam_max, double* theta_min,
+                 double* theta_max, ovl_stream_t s);
+int ovl_hw_eigs(const ovl_gauge* u, double rho, int ell, int m, void* V, double* lambda, double lam_max, double tol,
+                int max_iter, int degree, ovl_eig_stats* stats, ovl_stream_t s);
+/* ovl_host_heev: eigen-decomposition of a Hermitian n x n matrix on the host
+ * (column-major complex128 A, read only); w: n ascending eigenvalues, V:
+ * n x n column-major complex128 eigenvectors.  The dense kernel the
+ * eigensolver uses for its Gram and Rayleigh-Ritz matrices.
+ */
+int ovl_host_heev(int n, const double* A, double* w, double* V);
+
+/* ovl_counters: stencil launches and vector applications of D_w issued from
+ * the host since the last reset (graph replays are not seen here).
+ */
+int ovl_counters(int64_t* stencil_launches, int64_t* stencil_vectors, int reset);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,6 +1,7 @@
 // extern "C" entry points of libovl: argument checks, error codes, and the
 // dispatch to the internal drivers.  Each function's contract is documented
 // in include/ovl.h.
+#include <atomic>
 #include <cstdio>
 
 #include "ops.h"
@@ -32,6 +33,14 @@ Pool& pool() {
 }  // namespace
 
 void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+namespace {
+std::atomic<int64_t> g_stencil_launches{0}, g_stencil_vectors{0};
+}
+void count_stencil(int nrhs) {
+  g_stencil_launches.fetch_add(1, std::memory_order_relaxed);
+  g_stencil_vectors.fetch_add(nrhs, std::memory_order_relaxed);
+}
 
 void* ws_get(size_t bytes, hipStream_t s) {
   Pool& P = pool();
@@ -72,6 +81,16 @@ extern "C" {
 const char* ovl_last_error(void) { return g_last_error.c_str(); }
 
 int ovl_version(void) { return 100; }
+
+int ovl_counters(int64_t* stencil_launches, int64_t* stencil_vectors, int reset) {
+  if (stencil_launches) *stencil_launches = g_stencil_launches.load();
+  if (stencil_vectors) *stencil_vectors = g_stencil_vectors.load();
+  if (reset) {
+    g_stencil_launches = 0;
+    g_stencil_vectors = 0;
+  }
+  return OVL_OK;
+}
 
 // ------------------------------------------------------------------ geometry
 int ovl_geom_create(const int32_t dims[4], ovl_geom** out) {

@@ -7,6 +7,8 @@
 // grid-stride share with wave64 shuffles and LDS, and a second one-block
 // kernel adds the per-block partials in a fixed order, so a given input
 // always gives the same bits.
+#include <type_traits>
+
 #include "ops.h"
 
 namespace ovl {
@@ -79,6 +81,49 @@ __global__ void gamma5_kernel(size_t n16, int Nh, const char* x, char* y, size_t
   for (int k = 0; k < cpb; ++k)
     if (j * cpb + k >= 6) v[k] = real(-1) * v[k];
   Block<P>::store(y + off, v);
+}
+
+// y(PY) = a x(PX) + b y(PY), per site, with complex a, b per rhs read from
+// device memory (a[2r], a[2r+1]); y is not read when READY is false.
+template <int PX, int PY, bool READY>
+__global__ void axpby_kernel(int Nh, const double* a, const char* x, const double* b, char* y, size_t sx,
+                             size_t sy) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 2 * Nh) return;
+  const int p = e >= Nh, h = e - p * Nh, r = blockIdx.y;
+  using rx = typename Prec<PX>::real;
+  using ry = typename Prec<PY>::real;
+  using rc = typename std::conditional<(sizeof(rx) > sizeof(ry)), rx, ry>::type;
+  Cx<rx> xv[12];
+  SpinorIO<PX>::load(x + r * sx, p, h, Nh, xv);
+  const Cx<rc> ar = {static_cast<rc>(a[2 * r]), static_cast<rc>(a[2 * r + 1])};
+  Cx<ry> out[12];
+  if constexpr (READY) {
+    Cx<ry> yv[12];
+    SpinorIO<PY>::load(y + r * sy, p, h, Nh, yv);
+    const Cx<rc> br = {static_cast<rc>(b[2 * r]), static_cast<rc>(b[2 * r + 1])};
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      const Cx<rc> xx = {static_cast<rc>(xv[k].re), static_cast<rc>(xv[k].im)};
+      const Cx<rc> yy = {static_cast<rc>(yv[k].re), static_cast<rc>(yv[k].im)};
+      const Cx<rc> z = ar * xx + br * yy;
+      out[k] = {static_cast<ry>(z.re), static_cast<ry>(z.im)};
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      const Cx<rc> xx = {static_cast<rc>(xv[k].re), static_cast<rc>(xv[k].im)};
+      const Cx<rc> z = ar * xx;
+      out[k] = {static_cast<ry>(z.re), static_cast<ry>(z.im)};
+    }
+  }
+  SpinorIO<PY>::store(y + r * sy, p, h, Nh, out);
+}
+
+// y = 0 (a fill kernel, so that it can live inside a captured graph)
+__global__ void zero_kernel(size_t n16, uint4* y) {
+  const size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x;
+  if (i < n16) y[i] = make_uint4(0u, 0u, 0u, 0u);
 }
 
 __device__ inline double wave_sum(double v) {
@@ -242,6 +287,49 @@ void blas_axpy(int prec, size_t n16, const double* a, const void* x, void* y, in
 void blas_xpay(int prec, size_t n16, const void* x, const double* a, void* y, int nrhs, size_t vstride,
                hipStream_t s) {
   dispatch_prec<XpayL>(prec, n16, x, a, y, nrhs, vstride, s);
+  OVL_HIP(hipGetLastError());
+}
+
+template <int PX, int PY>
+void axpby_go(int Nh, const double* a, const void* x, const double* b, void* y, int nrhs, hipStream_t s) {
+  const size_t sx = static_cast<size_t>(2) * Nh * spinor_bytes_per_site(PX);
+  const size_t sy = static_cast<size_t>(2) * Nh * spinor_bytes_per_site(PY);
+  dim3 grid((2 * Nh + 255) / 256, nrhs);
+  if (b)
+    hipLaunchKernelGGL((axpby_kernel<PX, PY, true>), grid, dim3(256), 0, s, Nh, a, static_cast<const char*>(x), b,
+                       static_cast<char*>(y), sx, sy);
+  else
+    hipLaunchKernelGGL((axpby_kernel<PX, PY, false>), grid, dim3(256), 0, s, Nh, a, static_cast<const char*>(x),
+                       b, static_cast<char*>(y), sx, sy);
+}
+
+template <int PX>
+void axpby_py(int py, int Nh, const double* a, const void* x, const double* b, void* y, int nrhs, hipStream_t s) {
+  switch (py) {
+    case OVL_F64: axpby_go<PX, OVL_F64>(Nh, a, x, b, y, nrhs, s); break;
+    case OVL_F32: axpby_go<PX, OVL_F32>(Nh, a, x, b, y, nrhs, s); break;
+    case OVL_F16: axpby_go<PX, OVL_F16>(Nh, a, x, b, y, nrhs, s); break;
+    case OVL_BF16: axpby_go<PX, OVL_BF16>(Nh, a, x, b, y, nrhs, s); break;
+    default: throw Error(OVL_E_PRECISION, "unknown precision");
+  }
+}
+
+void blas_axpby(int px, const void* x, const double* a, int py, void* y, const double* b, size_t nsites, int nrhs,
+                hipStream_t s) {
+  const int Nh = static_cast<int>(nsites / 2);
+  switch (px) {
+    case OVL_F64: axpby_py<OVL_F64>(py, Nh, a, x, b, y, nrhs, s); break;
+    case OVL_F32: axpby_py<OVL_F32>(py, Nh, a, x, b, y, nrhs, s); break;
+    case OVL_F16: axpby_py<OVL_F16>(py, Nh, a, x, b, y, nrhs, s); break;
+    case OVL_BF16: axpby_py<OVL_BF16>(py, Nh, a, x, b, y, nrhs, s); break;
+    default: throw Error(OVL_E_PRECISION, "unknown precision");
+  }
+  OVL_HIP(hipGetLastError());
+}
+
+void blas_zero(void* y, size_t bytes, hipStream_t s) {
+  const size_t n16 = bytes / 16;
+  hipLaunchKernelGGL(zero_kernel, dim3((n16 + 255) / 256), dim3(256), 0, s, n16, static_cast<uint4*>(y));
   OVL_HIP(hipGetLastError());
 }
 

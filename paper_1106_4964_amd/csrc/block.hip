@@ -1,0 +1,341 @@
+// Tall-skinny block operations between a set of FP64 basis vectors V
+// (eigenvectors, Krylov or subspace bases) and a batch of R <= 12 spinors:
+//
+//   block_dot   : C[i][r] = V_i^dag psi_r             (FP64 accumulation)
+//   block_axpy  : Y_r     = [Y_r] + sum_i V_i K[i][r]
+//   lowmode_project (eq. 6-7 of arXiv:1106.4964):
+//       psi_h = psi - sum_i (V_i^dag psi) V_i,
+//       w     = [gamma5] sum_i sign(lambda_i) (V_i^dag psi) V_i
+//
+// Both sweeps read V exactly once.  Elements are walked in "rows"
+// (parity p, complex index c) of N/2 sites, so a complex number is addressed
+// the same way whatever the storage precision of the batch.
+//
+// block_dot is a split-K product: each block of a 512-block grid takes a
+// contiguous range of 64-element tiles, stages the batch tile in LDS, and
+// every wave accumulates IW basis vectors against it in registers; a second
+// kernel adds the per-block partials in block order, so results are
+// bit-reproducible.
+#include "ops.h"
+
+namespace ovl {
+namespace {
+
+template <int P>
+__device__ inline size_t cx_offset(int row, int h, int Nh) {
+  constexpr int cpb = Prec<P>::cpb;
+  const int p = row / 12, c = row % 12;
+  const size_t blk = (static_cast<size_t>(p) * (12 / cpb) + c / cpb) * Nh + h;
+  return blk * 16 + (c % cpb) * (16 / cpb);
+}
+
+template <int P>
+__device__ inline Cx<double> load_cx(const char* base, int row, int h, int Nh) {
+  Cx<typename Prec<P>::real> v = ScalarIO<P>::load1(base + cx_offset<P>(row, h, Nh));
+  return {static_cast<double>(v.re), static_cast<double>(v.im)};
+}
+
+template <int P>
+__device__ inline void store_cx(char* base, int row, int h, int Nh, Cx<double> v) {
+  using real = typename Prec<P>::real;
+  ScalarIO<P>::store1(base + cx_offset<P>(row, h, Nh), Cx<real>{static_cast<real>(v.re), static_cast<real>(v.im)});
+}
+
+constexpr int PJ_TILE = 64;     // elements per tile (one per lane)
+constexpr int PJ_WAVES = 8;     // waves per block of block_dot
+constexpr int PJ_BLOCKS = 512;  // K-split of block_dot
+
+__device__ inline double wsum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// partial[(i*G + b)*R + r] = sum over block b's tiles of conj(V_i) psi_r.
+// blockIdx.y selects a group of PJ_WAVES*IW basis vectors; each wave owns IW.
+template <int PP, int RMAX, int IW>
+__global__ __launch_bounds__(PJ_WAVES * 64) void dot_kernel(int Nh, int ell, const char* V, size_t vstrideV,
+                                                             const char* psi, size_t vstrideP, int R,
+                                                             double2* partial) {
+  __shared__ Cx<double> tile[RMAX][PJ_TILE];
+  const int tiles_per_row = (Nh + PJ_TILE - 1) / PJ_TILE;
+  const long total = 24L * tiles_per_row;
+  const long t0 = total * blockIdx.x / gridDim.x, t1 = total * (blockIdx.x + 1) / gridDim.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int ibase = (blockIdx.y * PJ_WAVES + wave) * IW;
+  Cx<double> acc[IW][RMAX];
+#pragma unroll
+  for (int j = 0; j < IW; ++j)
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r) acc[j][r] = {0.0, 0.0};
+
+  for (long t = t0; t < t1; ++t) {
+    const int row = static_cast<int>(t / tiles_per_row);
+    const int h0 = static_cast<int>(t % tiles_per_row) * PJ_TILE;
+    __syncthreads();
+    for (int k = threadIdx.x; k < R * PJ_TILE; k += blockDim.x) {
+      const int r = k / PJ_TILE, l = k % PJ_TILE;
+      tile[r][l] = (h0 + l < Nh) ? load_cx<PP>(psi + r * vstrideP, row, h0 + l, Nh) : Cx<double>{0.0, 0.0};
+    }
+    __syncthreads();
+    const int h = h0 + lane;
+    if (h < Nh) {
+      Cx<double> ps[RMAX];
+#pragma unroll
+      for (int r = 0; r < RMAX; ++r) ps[r] = (r < R) ? tile[r][lane] : Cx<double>{0.0, 0.0};
+#pragma unroll
+      for (int j = 0; j < IW; ++j) {
+        const int i = ibase + j;
+        if (i < ell) {
+          const Cx<double> v = load_cx<OVL_F64>(V + i * vstrideV, row, h, Nh);
+#pragma unroll
+          for (int r = 0; r < RMAX; ++r) acc[j][r] = acc[j][r] + cmul_conj(v, ps[r]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < IW; ++j) {
+    const int i = ibase + j;
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r) {
+      const double re = wsum(acc[j][r].re), im = wsum(acc[j][r].im);
+      if (lane == 0 && i < ell && r < R)
+        partial[(static_cast<size_t>(i) * gridDim.x + blockIdx.x) * R + r] = make_double2(re, im);
+    }
+  }
+}
+
+// C[i*R + r] = sum_b partial[(i*G + b)*R + r], in block order.
+__global__ void dot_reduce_kernel(int ell, int R, int G, const double2* partial, double2* C) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= ell * R) return;
+  const int i = k / R, r = k % R;
+  double re = 0.0, im = 0.0;
+  for (int b = 0; b < G; ++b) {
+    const double2 v = partial[(static_cast<size_t>(i) * G + b) * R + r];
+    re += v.x;
+    im += v.y;
+  }
+  C[k] = make_double2(re, im);
+}
+
+// Y_r = [Y_r] + sum_i V_i K[i*R + r]; one thread per element, K in LDS.
+template <int PP, int RMAX, bool KEEP>
+__global__ __launch_bounds__(256) void axpy_kernel(int Nh, int ell, const char* V, size_t vstrideV,
+                                                   const double2* K, char* Y, size_t vstrideP, int R) {
+  extern __shared__ double2 coef[];
+  for (int k = threadIdx.x; k < ell * R; k += blockDim.x) coef[k] = K[k];
+  __syncthreads();
+  const int row = blockIdx.y;
+  const int h = blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= Nh) return;
+  Cx<double> y[RMAX];
+#pragma unroll
+  for (int r = 0; r < RMAX; ++r)
+    y[r] = (KEEP && r < R) ? load_cx<PP>(Y + r * vstrideP, row, h, Nh) : Cx<double>{0.0, 0.0};
+  for (int i = 0; i < ell; ++i) {
+    const Cx<double> v = load_cx<OVL_F64>(V + i * vstrideV, row, h, Nh);
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r) {
+      if (r < R) {
+        const double2 cc = coef[i * R + r];
+        y[r] = y[r] + v * Cx<double>{cc.x, cc.y};
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < RMAX; ++r)
+    if (r < R) store_cx<PP>(Y + r * vstrideP, row, h, Nh, y[r]);
+}
+
+// psi_h = psi - sum_i C_i eta_i, w = [gamma5] sum_i sign_i C_i eta_i.
+template <int PP, int RMAX>
+__global__ __launch_bounds__(256) void project_kernel(int Nh, int ell, const char* V, size_t vstrideV,
+                                                      const char* psi, char* psih, char* w, size_t vstrideP, int R,
+                                                      const double2* C, const double* sgn, int g5w) {
+  extern __shared__ double2 coef[];
+  for (int k = threadIdx.x; k < ell * R; k += blockDim.x) coef[k] = C[k];
+  __syncthreads();
+  const int row = blockIdx.y;
+  const int h = blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= Nh) return;
+  Cx<double> ph[RMAX], ww[RMAX];
+#pragma unroll
+  for (int r = 0; r < RMAX; ++r) {
+    ph[r] = (r < R) ? load_cx<PP>(psi + r * vstrideP, row, h, Nh) : Cx<double>{0.0, 0.0};
+    ww[r] = {0.0, 0.0};
+  }
+  for (int i = 0; i < ell; ++i) {
+    const Cx<double> v = load_cx<OVL_F64>(V + i * vstrideV, row, h, Nh);
+    const double s = sgn[i];
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r) {
+      if (r < R) {
+        const double2 cc = coef[i * R + r];
+        const Cx<double> vc = v * Cx<double>{cc.x, cc.y};
+        ph[r] = ph[r] - vc;
+        ww[r] = ww[r] + s * vc;
+      }
+    }
+  }
+  const double gs = (g5w && (row % 12) >= 6) ? -1.0 : 1.0;  // spins 2, 3 under gamma5
+#pragma unroll
+  for (int r = 0; r < RMAX; ++r) {
+    if (r < R) {
+      store_cx<PP>(psih + r * vstrideP, row, h, Nh, ph[r]);
+      store_cx<PP>(w + r * vstrideP, row, h, Nh, gs * ww[r]);
+    }
+  }
+}
+
+// In-place basis rotation V[:, j] = sum_{i<K} V[:, i] S[i + K j], j < k.
+// Each block stages all K values of RT consecutive elements of one row in
+// LDS, so every element is read once and rewritten by the same block.
+constexpr int RT = 8;
+__global__ __launch_bounds__(256) void rotate_kernel(int Nh, int K, int k, char* V, size_t vstride,
+                                                     const double2* S) {
+  extern __shared__ Cx<double> vt[];  // [K][RT]
+  const int row = blockIdx.y;
+  const int h0 = blockIdx.x * RT;
+  for (int idx = threadIdx.x; idx < K * RT; idx += blockDim.x) {
+    const int i = idx / RT, e = idx % RT;
+    vt[idx] = (h0 + e < Nh) ? load_cx<OVL_F64>(V + i * vstride, row, h0 + e, Nh) : Cx<double>{0.0, 0.0};
+  }
+  __syncthreads();
+  const int e = threadIdx.x % RT;
+  for (int j = threadIdx.x / RT; j < k; j += blockDim.x / RT) {
+    Cx<double> acc = {0.0, 0.0};
+    const double2* sj = S + static_cast<size_t>(K) * j;
+    for (int i = 0; i < K; ++i) {
+      const double2 c = sj[i];
+      acc = acc + vt[i * RT + e] * Cx<double>{c.x, c.y};
+    }
+    if (h0 + e < Nh) store_cx<OVL_F64>(V + j * vstride, row, h0 + e, Nh, acc);
+  }
+}
+
+template <int PP, int RMAX, int IW>
+void dot_go(const ovl_geom* g, const void* V, int ell, const void* psi, int R, double2* C, hipStream_t s) {
+  const int Nh = g->geo.Nh;
+  const size_t vsV = spinor_vec_bytes(g, OVL_F64), vsP = spinor_vec_bytes(g, PP);
+  const int groups = (ell + PJ_WAVES * IW - 1) / (PJ_WAVES * IW);
+  WsBuf part(static_cast<size_t>(ell) * PJ_BLOCKS * R * sizeof(double2), s);
+  hipLaunchKernelGGL((dot_kernel<PP, RMAX, IW>), dim3(PJ_BLOCKS, groups), dim3(PJ_WAVES * 64), 0, s, Nh, ell,
+                     static_cast<const char*>(V), vsV, static_cast<const char*>(psi), vsP, R,
+                     static_cast<double2*>(part.p));
+  OVL_HIP(hipGetLastError());
+  hipLaunchKernelGGL(dot_reduce_kernel, dim3((ell * R + 255) / 256), dim3(256), 0, s, ell, R, PJ_BLOCKS,
+                     static_cast<const double2*>(part.p), C);
+  OVL_HIP(hipGetLastError());
+}
+
+template <int PP>
+void dot_r(const ovl_geom* g, const void* V, int ell, const void* psi, int R, double2* C, hipStream_t s) {
+  if (R == 1) dot_go<PP, 1, 8>(g, V, ell, psi, R, C, s);
+  else if (R <= 4) dot_go<PP, 4, 4>(g, V, ell, psi, R, C, s);
+  else dot_go<PP, 12, 2>(g, V, ell, psi, R, C, s);
+}
+
+size_t coef_lds(int ell, int R) {
+  const size_t lds = static_cast<size_t>(ell) * R * sizeof(double2);
+  OVL_REQUIRE(lds <= 64 * 1024, OVL_E_ARG, "block operation: basis size * nrhs too large (max 4096)");
+  return lds;
+}
+
+template <int PP, int RMAX>
+void axpy_go(const ovl_geom* g, const void* V, int ell, const double2* K, void* Y, int R, bool keep, hipStream_t s) {
+  const int Nh = g->geo.Nh;
+  const size_t vsV = spinor_vec_bytes(g, OVL_F64), vsP = spinor_vec_bytes(g, PP);
+  const size_t lds = coef_lds(ell, R);
+  dim3 grid((Nh + 255) / 256, 24);
+  if (keep)
+    hipLaunchKernelGGL((axpy_kernel<PP, RMAX, true>), grid, dim3(256), lds, s, Nh, ell, static_cast<const char*>(V),
+                       vsV, K, static_cast<char*>(Y), vsP, R);
+  else
+    hipLaunchKernelGGL((axpy_kernel<PP, RMAX, false>), grid, dim3(256), lds, s, Nh, ell,
+                       static_cast<const char*>(V), vsV, K, static_cast<char*>(Y), vsP, R);
+  OVL_HIP(hipGetLastError());
+}
+
+template <int PP>
+void axpy_r(const ovl_geom* g, const void* V, int ell, const double2* K, void* Y, int R, bool keep, hipStream_t s) {
+  if (R == 1) axpy_go<PP, 1>(g, V, ell, K, Y, R, keep, s);
+  else if (R <= 4) axpy_go<PP, 4>(g, V, ell, K, Y, R, keep, s);
+  else axpy_go<PP, 12>(g, V, ell, K, Y, R, keep, s);
+}
+
+template <int PP, int RMAX>
+void project_go(const ovl_lowmodes* lm, const void* psi, void* psih, void* w, int R, int g5w, const double2* C,
+                hipStream_t s) {
+  const ovl_geom* g = &lm->geom;
+  const int Nh = g->geo.Nh;
+  const size_t vsV = spinor_vec_bytes(g, OVL_F64), vsP = spinor_vec_bytes(g, PP);
+  const size_t lds = coef_lds(lm->ell, R);
+  hipLaunchKernelGGL((project_kernel<PP, RMAX>), dim3((Nh + 255) / 256, 24), dim3(256), lds, s, Nh, lm->ell,
+                     static_cast<const char*>(lm->V), vsV, static_cast<const char*>(psi), static_cast<char*>(psih),
+                     static_cast<char*>(w), vsP, R, C, lm->dev_sign, g5w);
+  OVL_HIP(hipGetLastError());
+}
+
+template <int PP>
+void project_r(const ovl_lowmodes* lm, const void* psi, void* psih, void* w, int R, int g5w, const double2* C,
+               hipStream_t s) {
+  if (R == 1) project_go<PP, 1>(lm, psi, psih, w, R, g5w, C, s);
+  else if (R <= 4) project_go<PP, 4>(lm, psi, psih, w, R, g5w, C, s);
+  else project_go<PP, 12>(lm, psi, psih, w, R, g5w, C, s);
+}
+
+}  // namespace
+
+void block_dot(const ovl_geom* g, const void* V, int ell, const void* psi, int prec, int R, double2* C,
+               hipStream_t s) {
+  OVL_REQUIRE(R >= 1 && R <= OVL_MAX_RHS && ell >= 1, OVL_E_ARG, "block_dot: 1 <= R <= 12, ell >= 1");
+  switch (prec) {
+    case OVL_F64: dot_r<OVL_F64>(g, V, ell, psi, R, C, s); break;
+    case OVL_F32: dot_r<OVL_F32>(g, V, ell, psi, R, C, s); break;
+    case OVL_F16: dot_r<OVL_F16>(g, V, ell, psi, R, C, s); break;
+    case OVL_BF16: dot_r<OVL_BF16>(g, V, ell, psi, R, C, s); break;
+    default: throw Error(OVL_E_PRECISION, "unknown precision");
+  }
+}
+
+void block_axpy(const ovl_geom* g, const void* V, int ell, const double2* K, void* Y, int prec, int R, bool keep,
+                hipStream_t s) {
+  OVL_REQUIRE(R >= 1 && R <= OVL_MAX_RHS && ell >= 1, OVL_E_ARG, "block_axpy: 1 <= R <= 12, ell >= 1");
+  switch (prec) {
+    case OVL_F64: axpy_r<OVL_F64>(g, V, ell, K, Y, R, keep, s); break;
+    case OVL_F32: axpy_r<OVL_F32>(g, V, ell, K, Y, R, keep, s); break;
+    case OVL_F16: axpy_r<OVL_F16>(g, V, ell, K, Y, R, keep, s); break;
+    case OVL_BF16: axpy_r<OVL_BF16>(g, V, ell, K, Y, R, keep, s); break;
+    default: throw Error(OVL_E_PRECISION, "unknown precision");
+  }
+}
+
+void block_rotate_inplace(const ovl_geom* g, void* V, int K, const double2* S, int k, hipStream_t s) {
+  OVL_REQUIRE(k >= 1 && k <= K, OVL_E_ARG, "rotate: need 1 <= k <= K");
+  const size_t lds = static_cast<size_t>(K) * RT * sizeof(Cx<double>);
+  OVL_REQUIRE(lds <= 64 * 1024, OVL_E_ARG, "rotate: basis too large (K <= 512)");
+  const int Nh = g->geo.Nh;
+  dim3 grid((Nh + RT - 1) / RT, 24);
+  hipLaunchKernelGGL(rotate_kernel, grid, dim3(256), lds, s, Nh, K, k, static_cast<char*>(V),
+                     spinor_vec_bytes(g, OVL_F64), S);
+  OVL_HIP(hipGetLastError());
+}
+
+void lowmode_project(const ovl_lowmodes* lm, const void* psi, void* psih, void* w, int prec, int nrhs, int g5w,
+                     hipStream_t s) {
+  OVL_REQUIRE(nrhs <= OVL_MAX_RHS, OVL_E_ARG, "projection supports at most 12 right-hand sides");
+  WsBuf cbuf(static_cast<size_t>(lm->ell) * nrhs * sizeof(double2), s);
+  double2* C = static_cast<double2*>(cbuf.p);
+  block_dot(&lm->geom, lm->V, lm->ell, psi, prec, nrhs, C, s);
+  switch (prec) {
+    case OVL_F64: project_r<OVL_F64>(lm, psi, psih, w, nrhs, g5w, C, s); break;
+    case OVL_F32: project_r<OVL_F32>(lm, psi, psih, w, nrhs, g5w, C, s); break;
+    case OVL_F16: project_r<OVL_F16>(lm, psi, psih, w, nrhs, g5w, C, s); break;
+    case OVL_BF16: project_r<OVL_BF16>(lm, psi, psih, w, nrhs, g5w, C, s); break;
+    default: throw Error(OVL_E_PRECISION, "unknown precision");
+  }
+}
+
+}  // namespace ovl

@@ -423,6 +423,21 @@ struct ovl_gauge {
   int recon[4] = {0, 0, 0, 0};                             // 18 or 12 (0 = absent)
 };
 
+struct ovl_sign {
+  double lam_max;
+  double eps;
+  double delta;           // measured max |1 - sqrt(x) P(x)| on [eps, 1]
+  std::vector<double> c;  // c_0..c_n, c_0 already halved
+};
+
+struct ovl_lowmodes {
+  ovl_geom geom;
+  int ell;
+  const void* V;  // borrowed: ell FP64 spinors
+  std::vector<double> lambda;
+  double* dev_sign = nullptr;  // sign(lambda_i) on the device
+};
+
 namespace ovl {
 
 // Device workspace pool.  A buffer released on stream s is only handed out

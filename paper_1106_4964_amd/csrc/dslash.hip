@@ -213,6 +213,7 @@ void launch_pr(const StencilArgs& A, int nrhs, hipStream_t s) {
 
 void launch_stencil(const StencilArgs& A, int prec, int recon, int nrhs, hipStream_t s) {
   OVL_REQUIRE(recon == 18 || recon == 12, OVL_E_PRECISION, "link representation missing");
+  count_stencil(nrhs);
   const bool r18 = recon == 18;
   switch (prec) {
     case OVL_F64: r18 ? launch_pr<OVL_F64, 18>(A, nrhs, s) : launch_pr<OVL_F64, 12>(A, nrhs, s); break;

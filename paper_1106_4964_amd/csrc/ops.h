@@ -42,6 +42,13 @@ void blas_xpay(int prec, size_t n16, const void* x, const double* a, void* y, in
 // y = gamma5 x for a batch of nrhs vectors of vstride bytes each.
 void blas_gamma5(int prec, size_t vstride, const void* x, void* y, int nrhs, hipStream_t s);
 void blas_convert(int sprec, const void* src, int dprec, void* dst, size_t nsites, int nrhs, hipStream_t s);
+// y(py) = a x(px) + b y(py) for a batch of nrhs lattice vectors (nsites
+// sites each); a, b: device arrays of one complex (re, im) per rhs; b may be
+// null (y = a x, y not read).  Arithmetic in the wider of the two types.
+void blas_axpby(int px, const void* x, const double* a, int py, void* y, const double* b, size_t nsites, int nrhs,
+                hipStream_t s);
+// y = 0 over `bytes` (a multiple of 16), as a kernel.
+void blas_zero(void* y, size_t bytes, hipStream_t s);
 // Deterministic two-stage reductions; results (re, im) per rhs written to
 // device memory dev_out[2*rhs].
 void blas_dot(int prec, size_t n16, const void* x, const void* y, int nrhs, size_t vstride, double* dev_out,
@@ -49,11 +56,32 @@ void blas_dot(int prec, size_t n16, const void* x, const void* y, int nrhs, size
 void blas_norm2(int prec, size_t n16, const void* x, int nrhs, size_t vstride, double* dev_out,
                 hipStream_t s);
 
+// ------------------------------------------------------- tall-skinny blocks
+// V: ell FP64 basis vectors (library layout, back to back); psi, Y: batch of
+// R <= 12 vectors at precision prec.  C, K: device arrays of ell*R complex,
+// index i*R + r.
+void block_dot(const ovl_geom* g, const void* V, int ell, const void* psi, int prec, int R, double2* C,
+               hipStream_t s);
+void block_axpy(const ovl_geom* g, const void* V, int ell, const double2* K, void* Y, int prec, int R, bool keep,
+                hipStream_t s);
+// In place: V[:, j] = sum_{i<K} V[:, i] S[i + K*j] for j < k (FP64 basis, S on the device, K <= 512).
+void block_rotate_inplace(const ovl_geom* g, void* V, int K, const double2* S, int k, hipStream_t s);
+
 // ------------------------------------------------------------ sign / overlap
 void lowmode_project(const ovl_lowmodes* lm, const void* psi, void* psih, void* w, int prec, int nrhs, int g5w,
                      hipStream_t s);
 // mode 0: sign(H_w) in;  1: D(m) in;  2: D(m)^dag in
 void overlap_apply(void* out, const void* in, const ovl_gauge* u, double rho, double m, const ovl_sign* sg,
                    const ovl_lowmodes* lm, int mode, int prec, int nrhs, hipStream_t s);
+// out = ap in + am gamma5 sign(H_w) in  (the general combine behind D(m))
+void overlap_combine(void* out, const void* in, const ovl_gauge* u, double rho, double ap, double am,
+                     const ovl_sign* sg, const ovl_lowmodes* lm, int prec, int nrhs, hipStream_t s);
+
+int cg_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, double m, const ovl_sign* sg,
+             const ovl_lowmodes* lm, double tol, int maxiter, const ovl_solve_opts* o, ovl_solve_stats* st,
+             hipStream_t us);
+
+// Counters of stencil work issued from the host (not counting graph replays).
+void count_stencil(int nrhs);
 
 }  // namespace ovl

@@ -20,21 +20,6 @@
 
 #include "ops.h"
 
-struct ovl_sign {
-  double lam_max;
-  double eps;
-  double delta;  // measured max |1 - sqrt(x) P(x)| on [eps, 1]
-  std::vector<double> c;  // c_0..c_n, c_0 already halved
-};
-
-struct ovl_lowmodes {
-  ovl_geom geom;
-  int ell;
-  const void* V;              // borrowed: ell FP64 spinors
-  std::vector<double> lambda;
-  double* dev_sign = nullptr;  // sign(lambda_i) on the device
-};
-
 namespace ovl {
 
 // ------------------------------------------------------------ coefficients
@@ -117,197 +102,6 @@ int sign_order(double eps, double target) {
     else lo = mid;
   }
   return hi;
-}
-
-namespace {
-
-// ------------------------------------------------------------- projection
-// Elements are walked in "rows" (parity p, complex index c): 24 rows of Nh
-// sites, so each complex of a vector is addressed the same way in every
-// storage precision.
-template <int P>
-__device__ inline size_t cx_offset(int row, int h, int Nh) {
-  constexpr int cpb = Prec<P>::cpb;
-  const int p = row / 12, c = row % 12;
-  const size_t blk = (static_cast<size_t>(p) * (12 / cpb) + c / cpb) * Nh + h;
-  return blk * 16 + (c % cpb) * (16 / cpb);
-}
-
-template <int P>
-__device__ inline Cx<double> load_cx(const char* base, int row, int h, int Nh) {
-  Cx<typename Prec<P>::real> v = ScalarIO<P>::load1(base + cx_offset<P>(row, h, Nh));
-  return {static_cast<double>(v.re), static_cast<double>(v.im)};
-}
-
-template <int P>
-__device__ inline void store_cx(char* base, int row, int h, int Nh, Cx<double> v) {
-  using real = typename Prec<P>::real;
-  ScalarIO<P>::store1(base + cx_offset<P>(row, h, Nh), Cx<real>{static_cast<real>(v.re), static_cast<real>(v.im)});
-}
-
-constexpr int PJ_TILE = 64;     // elements per tile (one per lane)
-constexpr int PJ_WAVES = 8;     // waves per block in pass 1
-constexpr int PJ_BLOCKS = 512;  // K-split of pass 1
-
-__device__ inline double wsum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-// Pass 1: partial[(i*G + b)*R + r] = sum over block b's tiles of conj(V_i) Psi_r.
-// blockIdx.y selects a group of PJ_WAVES*IW eigenvectors; each wave owns IW.
-template <int PP, int RMAX, int IW>
-__global__ __launch_bounds__(PJ_WAVES * 64) void proj_dot_kernel(int Nh, int ell, const char* V, size_t vstrideV,
-                                                                  const char* psi, size_t vstrideP, int R,
-                                                                  double2* partial) {
-  __shared__ Cx<double> tile[RMAX][PJ_TILE];
-  const int tiles_per_row = (Nh + PJ_TILE - 1) / PJ_TILE;
-  const long total = 24L * tiles_per_row;
-  const long t0 = total * blockIdx.x / gridDim.x, t1 = total * (blockIdx.x + 1) / gridDim.x;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int ibase = (blockIdx.y * PJ_WAVES + wave) * IW;
-  Cx<double> acc[IW][RMAX];
-#pragma unroll
-  for (int j = 0; j < IW; ++j)
-#pragma unroll
-    for (int r = 0; r < RMAX; ++r) acc[j][r] = {0.0, 0.0};
-
-  for (long t = t0; t < t1; ++t) {
-    const int row = static_cast<int>(t / tiles_per_row);
-    const int h0 = static_cast<int>(t % tiles_per_row) * PJ_TILE;
-    __syncthreads();
-    for (int k = threadIdx.x; k < R * PJ_TILE; k += blockDim.x) {
-      const int r = k / PJ_TILE, l = k % PJ_TILE;
-      tile[r][l] = (h0 + l < Nh) ? load_cx<PP>(psi + r * vstrideP, row, h0 + l, Nh) : Cx<double>{0.0, 0.0};
-    }
-    __syncthreads();
-    const int h = h0 + lane;
-    if (h < Nh) {
-      Cx<double> ps[RMAX];
-#pragma unroll
-      for (int r = 0; r < RMAX; ++r) ps[r] = (r < R) ? tile[r][lane] : Cx<double>{0.0, 0.0};
-#pragma unroll
-      for (int j = 0; j < IW; ++j) {
-        const int i = ibase + j;
-        if (i < ell) {
-          const Cx<double> v = load_cx<OVL_F64>(V + i * vstrideV, row, h, Nh);
-#pragma unroll
-          for (int r = 0; r < RMAX; ++r) acc[j][r] = acc[j][r] + cmul_conj(v, ps[r]);
-        }
-      }
-    }
-  }
-#pragma unroll
-  for (int j = 0; j < IW; ++j) {
-    const int i = ibase + j;
-#pragma unroll
-    for (int r = 0; r < RMAX; ++r) {
-      const double re = wsum(acc[j][r].re), im = wsum(acc[j][r].im);
-      if (lane == 0 && i < ell && r < R)
-        partial[(static_cast<size_t>(i) * gridDim.x + blockIdx.x) * R + r] = make_double2(re, im);
-    }
-  }
-}
-
-// C[i*R + r] = sum_b partial[(i*G + b)*R + r], in block order.
-__global__ void proj_reduce_kernel(int ell, int R, int G, const double2* partial, double2* C) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= ell * R) return;
-  const int i = k / R, r = k % R;
-  double re = 0.0, im = 0.0;
-  for (int b = 0; b < G; ++b) {
-    const double2 v = partial[(static_cast<size_t>(i) * G + b) * R + r];
-    re += v.x;
-    im += v.y;
-  }
-  C[k] = make_double2(re, im);
-}
-
-// Pass 2: psi_h = psi - sum_i C_i eta_i, w = G5? sum_i sign_i C_i eta_i.
-// One thread per element; coefficients staged in LDS (broadcast reads).
-template <int PP, int RMAX>
-__global__ __launch_bounds__(256) void proj_update_kernel(int Nh, int ell, const char* V, size_t vstrideV,
-                                                          const char* psi, char* psih, char* w, size_t vstrideP,
-                                                          int R, const double2* C, const double* sgn, int g5w) {
-  extern __shared__ double2 coef[];  // [ell][R] of C, then [ell] signs folded in at use
-  for (int k = threadIdx.x; k < ell * R; k += blockDim.x) coef[k] = C[k];
-  __syncthreads();
-  const int row = blockIdx.y;
-  const int h = blockIdx.x * blockDim.x + threadIdx.x;
-  if (h >= Nh) return;
-  Cx<double> ph[RMAX], ww[RMAX];
-#pragma unroll
-  for (int r = 0; r < RMAX; ++r) {
-    ph[r] = (r < R) ? load_cx<PP>(psi + r * vstrideP, row, h, Nh) : Cx<double>{0.0, 0.0};
-    ww[r] = {0.0, 0.0};
-  }
-  for (int i = 0; i < ell; ++i) {
-    const Cx<double> v = load_cx<OVL_F64>(V + i * vstrideV, row, h, Nh);
-    const double s = sgn[i];
-#pragma unroll
-    for (int r = 0; r < RMAX; ++r) {
-      if (r < R) {
-        const double2 cc = coef[i * R + r];
-        const Cx<double> vc = v * Cx<double>{cc.x, cc.y};
-        ph[r] = ph[r] - vc;
-        ww[r] = ww[r] + s * vc;
-      }
-    }
-  }
-  const double gs = (g5w && (row % 12) >= 6) ? -1.0 : 1.0;  // spin 2,3 of gamma5
-#pragma unroll
-  for (int r = 0; r < RMAX; ++r) {
-    if (r < R) {
-      store_cx<PP>(psih + r * vstrideP, row, h, Nh, ph[r]);
-      store_cx<PP>(w + r * vstrideP, row, h, Nh, gs * ww[r]);
-    }
-  }
-}
-
-template <int PP, int RMAX, int IW>
-void proj_launch(const ovl_lowmodes* lm, const void* psi, void* psih, void* w, int R, int g5w, hipStream_t s) {
-  const ovl_geom* g = &lm->geom;
-  const int Nh = g->geo.Nh, ell = lm->ell;
-  const size_t vsV = spinor_vec_bytes(g, OVL_F64), vsP = spinor_vec_bytes(g, PP);
-  const int groups = (ell + PJ_WAVES * IW - 1) / (PJ_WAVES * IW);
-  WsBuf part(static_cast<size_t>(ell) * PJ_BLOCKS * R * sizeof(double2), s);
-  WsBuf cbuf(static_cast<size_t>(ell) * R * sizeof(double2), s);
-  hipLaunchKernelGGL((proj_dot_kernel<PP, RMAX, IW>), dim3(PJ_BLOCKS, groups), dim3(PJ_WAVES * 64), 0, s, Nh, ell,
-                     static_cast<const char*>(lm->V), vsV, static_cast<const char*>(psi), vsP, R,
-                     static_cast<double2*>(part.p));
-  OVL_HIP(hipGetLastError());
-  hipLaunchKernelGGL(proj_reduce_kernel, dim3((ell * R + 255) / 256), dim3(256), 0, s, ell, R, PJ_BLOCKS,
-                     static_cast<const double2*>(part.p), static_cast<double2*>(cbuf.p));
-  OVL_HIP(hipGetLastError());
-  const size_t lds = static_cast<size_t>(ell) * R * sizeof(double2);
-  OVL_REQUIRE(lds <= 64 * 1024, OVL_E_ARG, "projection: ell * nrhs too large (max 4096)");
-  hipLaunchKernelGGL((proj_update_kernel<PP, RMAX>), dim3((Nh + 255) / 256, 24), dim3(256), lds, s, Nh, ell,
-                     static_cast<const char*>(lm->V), vsV, static_cast<const char*>(psi), static_cast<char*>(psih),
-                     static_cast<char*>(w), vsP, R, static_cast<const double2*>(cbuf.p), lm->dev_sign, g5w);
-  OVL_HIP(hipGetLastError());
-}
-
-template <int PP>
-void proj_rmax(const ovl_lowmodes* lm, const void* psi, void* psih, void* w, int R, int g5w, hipStream_t s) {
-  if (R == 1) proj_launch<PP, 1, 8>(lm, psi, psih, w, R, g5w, s);
-  else if (R <= 4) proj_launch<PP, 4, 4>(lm, psi, psih, w, R, g5w, s);
-  else proj_launch<PP, 12, 2>(lm, psi, psih, w, R, g5w, s);
-}
-
-}  // namespace
-
-// psi_h and w for a batch of nrhs spinors (precision prec); w gets gamma5
-// applied when g5w is set.  psi may not alias psi_h or w.
-void lowmode_project(const ovl_lowmodes* lm, const void* psi, void* psih, void* w, int prec, int nrhs, int g5w,
-                     hipStream_t s) {
-  OVL_REQUIRE(nrhs <= OVL_MAX_RHS, OVL_E_ARG, "projection supports at most 12 right-hand sides");
-  switch (prec) {
-    case OVL_F64: proj_rmax<OVL_F64>(lm, psi, psih, w, nrhs, g5w, s); break;
-    case OVL_F32: proj_rmax<OVL_F32>(lm, psi, psih, w, nrhs, g5w, s); break;
-    case OVL_F16: proj_rmax<OVL_F16>(lm, psi, psih, w, nrhs, g5w, s); break;
-    case OVL_BF16: proj_rmax<OVL_BF16>(lm, psi, psih, w, nrhs, g5w, s); break;
-  }
 }
 
 // ------------------------------------------------------------- Clenshaw
@@ -425,9 +219,11 @@ void clenshaw_sign(const Stencil& st, const ovl_sign* sg, const void* psih, void
     st.apply(out, pin, sc, fg5, {}, {});
 }
 
-// Overlap-operator driver.  mode: 0 = sign(H_w) in, 1 = D(m) in, 2 = D(m)^dag in.
-void overlap_apply(void* out, const void* in, const ovl_gauge* u, double rho, double m, const ovl_sign* sg,
-                   const ovl_lowmodes* lm, int mode, int prec, int nrhs, hipStream_t s) {
+namespace {
+// mode: 0 = sign(H_w) in, 1 = ap in + am gamma5 sign(H_w) in,
+//       2 = ap in + am sign(H_w) gamma5 in.
+void overlap_driver(void* out, const void* in, const ovl_gauge* u, double rho, double ap, double am,
+                    const ovl_sign* sg, const ovl_lowmodes* lm, int mode, int prec, int nrhs, hipStream_t s) {
   Stencil st;
   st.u = u;
   st.links = gauge_links(u, prec, &st.recon);
@@ -455,7 +251,6 @@ void overlap_apply(void* out, const void* in, const ovl_gauge* u, double rho, do
     psih = hbuf.p;
     w = wbuf.p;
   }
-  const double ap = rho + 0.5 * m, am = rho - 0.5 * m;
   if (mode == 0) {
     // sign = (1/lam) H_w P + w
     clenshaw_sign(st, sg, psih, out, 1.0 / lam, 1, w, 1.0, nullptr, 0.0, 0);
@@ -466,6 +261,17 @@ void overlap_apply(void* out, const void* in, const ovl_gauge* u, double rho, do
     // D(m)^dag in = ap in + am sign(gamma5 in) = (am/lam) H_w P + ap in + am w
     clenshaw_sign(st, sg, psih, out, am / lam, 1, in, ap, w, am, 0);
   }
+}
+}  // namespace
+
+void overlap_apply(void* out, const void* in, const ovl_gauge* u, double rho, double m, const ovl_sign* sg,
+                   const ovl_lowmodes* lm, int mode, int prec, int nrhs, hipStream_t s) {
+  overlap_driver(out, in, u, rho, rho + 0.5 * m, rho - 0.5 * m, sg, lm, mode, prec, nrhs, s);
+}
+
+void overlap_combine(void* out, const void* in, const ovl_gauge* u, double rho, double ap, double am,
+                     const ovl_sign* sg, const ovl_lowmodes* lm, int prec, int nrhs, hipStream_t s) {
+  overlap_driver(out, in, u, rho, ap, am, sg, lm, 1, prec, nrhs, s);
 }
 
 }  // namespace ovl

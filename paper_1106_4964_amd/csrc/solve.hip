@@ -1,0 +1,340 @@
+// CG for quark propagators (arXiv:1106.4964 Sec. II, Sec. V).
+//
+// Solves D(m) x = b for a batch of right-hand sides by CG on
+// A = D(m) D(m)^dag with x = D(m)^dag y (Craig's method), so the recursively
+// updated residual is b - D(m) x.  An outer loop recomputes the true
+// residual in FP64 and restarts the inner solve on it (defect correction)
+// until every rhs has ||b - D(m) x|| <= tol ||b||.  The inner solve runs at
+// the storage precision the caller asks for (FP64 gives plain FP64 CG); its
+// correction is accumulated in FP64.
+//
+// Every Krylov scalar lives on the device: reductions write FP64 results to
+// device memory, tiny kernels turn them into alpha/beta and per-rhs
+// activity masks, and the vector kernels read them from there.  Nothing in
+// an inner iteration needs the host, so a chunk of iterations can be
+// captured once in a HIP graph and replayed; the host only reads the masks
+// between replays.
+#include <chrono>
+#include <cmath>
+
+#include "ops.h"
+
+namespace ovl {
+namespace {
+
+// Scalars of one inner solve, all device-resident, one slot per rhs.
+struct Scalars {
+  double rr[OVL_MAX_RHS];
+  double rrn[OVL_MAX_RHS];
+  double pp[OVL_MAX_RHS];
+  double target[OVL_MAX_RHS];
+  double alpha[2 * OVL_MAX_RHS];   // complex (a, 0)
+  double malpha[2 * OVL_MAX_RHS];  // complex (-a, 0)
+  double beta[2 * OVL_MAX_RHS];
+  double one[2 * OVL_MAX_RHS];
+  double mone[2 * OVL_MAX_RHS];
+  double scale[2 * OVL_MAX_RHS];   // rhs scale factors of the inner system
+  double iscale[2 * OVL_MAX_RHS];
+  double dot_tmp[2 * OVL_MAX_RHS];
+  int active[OVL_MAX_RHS];
+  int bad[OVL_MAX_RHS];  // 1 breakdown (p^dag p <= 0), 2 NaN/Inf
+};
+
+// dot results arrive as (re, im) pairs; keep the real parts.
+__global__ void take_real_kernel(int R, const double* d, double* out) {
+  const int r = threadIdx.x;
+  if (r < R) out[r] = d[2 * r];
+}
+
+__global__ void alpha_kernel(int R, Scalars* S) {
+  const int r = threadIdx.x;
+  if (r >= R) return;
+  double a = 0.0;
+  if (S->active[r]) {
+    const double pp = S->pp[r], rr = S->rr[r];
+    if (!(pp == pp) || !(rr == rr) || isinf(pp) || isinf(rr)) {
+      S->bad[r] = 2;
+      S->active[r] = 0;
+    } else if (pp <= 0.0) {
+      S->bad[r] = 1;
+      S->active[r] = 0;
+    } else {
+      a = rr / pp;
+    }
+  }
+  S->alpha[2 * r] = a;
+  S->alpha[2 * r + 1] = 0.0;
+  S->malpha[2 * r] = -a;
+  S->malpha[2 * r + 1] = 0.0;
+}
+
+__global__ void beta_kernel(int R, Scalars* S) {
+  const int r = threadIdx.x;
+  if (r >= R) return;
+  double b = 0.0;
+  if (S->active[r]) {
+    const double rrn = S->rrn[r];
+    if (!(rrn == rrn) || isinf(rrn)) {
+      S->bad[r] = 2;
+      S->active[r] = 0;
+    } else {
+      b = rrn / S->rr[r];
+      S->rr[r] = rrn;
+      if (rrn <= S->target[r]) S->active[r] = 0;
+    }
+  }
+  if (!S->active[r]) b = 0.0;
+  S->beta[2 * r] = b;
+  S->beta[2 * r + 1] = 0.0;
+}
+
+struct Solver {
+  const ovl_gauge* u;
+  double rho, m;
+  const ovl_sign* sg;
+  const ovl_lowmodes* lm;
+  int R, P;
+  hipStream_t s;
+  size_t v64, vP, nsites;
+  ovl_solve_stats* st;
+  int64_t per_sign_dw;
+
+  void dm(void* out, const void* in, int prec, int dagger) {
+    overlap_apply(out, in, u, rho, m, sg, lm, dagger ? 2 : 1, prec, R, s);
+    st->sign_applies += R;
+    st->dslash_applies += R * per_sign_dw;
+  }
+  void norm2(const void* x, int prec, double* dev_out, Scalars* S) {
+    blas_norm2(prec, (prec == OVL_F64 ? v64 : vP) / 16, x, R, prec == OVL_F64 ? v64 : vP, S->dot_tmp, s);
+    hipLaunchKernelGGL(take_real_kernel, dim3(1), dim3(64), 0, s, R, S->dot_tmp, dev_out);
+  }
+};
+
+}  // namespace
+
+int cg_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, double m, const ovl_sign* sg,
+             const ovl_lowmodes* lm, double tol, int maxiter, const ovl_solve_opts* o, ovl_solve_stats* st,
+             hipStream_t us) {
+  const auto t_start = std::chrono::steady_clock::now();
+  ovl_solve_opts def{};
+  def.inner_prec = OVL_F64;
+  def.inner_tol = 0.0;
+  def.graph_chunk = 0;
+  def.check_every = 1;
+  def.max_restarts = 50;
+  const ovl_solve_opts& opt = o ? *o : def;
+  const int P = opt.inner_prec;
+  check_prec(P);
+  const int check_every = std::max(1, opt.check_every);
+
+  Solver S{};
+  S.u = u;
+  S.rho = rho;
+  S.m = m;
+  S.sg = sg;
+  S.lm = lm;
+  S.R = R;
+  S.P = P;
+  S.st = st;
+  S.nsites = static_cast<size_t>(u->geom.N);
+  S.v64 = spinor_vec_bytes(&u->geom, OVL_F64);
+  S.vP = spinor_vec_bytes(&u->geom, P);
+  S.per_sign_dw = 2 * (static_cast<int64_t>(sg->c.size()) - 1) + 1;
+  int recon = 0;
+  (void)gauge_links(u, P, &recon);  // the inner precision must have links
+
+  // private stream (graph capture needs one), ordered after the caller's work
+  hipStream_t s;
+  OVL_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  S.s = s;
+  hipEvent_t ev;
+  OVL_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  OVL_HIP(hipEventRecord(ev, us));
+  OVL_HIP(hipStreamWaitEvent(s, ev, 0));
+
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  int rc = OVL_OK;
+  try {
+    WsBuf r64(S.v64 * R, s), tmp64(S.v64 * R, s), e64(S.v64 * R, s);
+    WsBuf rin(S.vP * R, s), p(S.vP * R, s), q(S.vP * R, s), t(S.vP * R, s);
+    WsBuf sbuf(sizeof(Scalars), s);
+    Scalars* dS = static_cast<Scalars*>(sbuf.p);
+    Scalars hS{};
+    for (int r = 0; r < R; ++r) {
+      hS.one[2 * r] = 1.0;
+      hS.mone[2 * r] = -1.0;
+    }
+    OVL_HIP(hipMemcpyAsync(dS, &hS, sizeof(Scalars), hipMemcpyHostToDevice, s));
+    OVL_HIP(hipStreamSynchronize(s));
+
+    // ||b||^2
+    std::vector<double> bn2(R), rn2(R);
+    S.norm2(b, OVL_F64, dS->rrn, dS);
+    OVL_HIP(hipMemcpyAsync(&hS.rrn, dS->rrn, sizeof(double) * R, hipMemcpyDeviceToHost, s));
+    OVL_HIP(hipStreamSynchronize(s));
+    for (int r = 0; r < R; ++r) {
+      bn2[r] = hS.rrn[r];
+      OVL_REQUIRE(std::isfinite(bn2[r]), OVL_E_NAN, "right-hand side contains NaN or Inf");
+    }
+
+    // inner-iteration body; records nothing but kernel launches
+    auto body = [&]() {
+      S.norm2(p.p, P, dS->pp, dS);
+      hipLaunchKernelGGL(alpha_kernel, dim3(1), dim3(64), 0, s, R, dS);
+      blas_axpby(P, p.p, dS->alpha, OVL_F64, e64.p, dS->one, S.nsites, R, s);
+      S.dm(q.p, p.p, P, 0);
+      blas_axpby(P, q.p, dS->malpha, P, rin.p, dS->one, S.nsites, R, s);
+      S.norm2(rin.p, P, dS->rrn, dS);
+      hipLaunchKernelGGL(beta_kernel, dim3(1), dim3(64), 0, s, R, dS);
+      S.dm(t.p, rin.p, P, 1);
+      blas_axpby(P, t.p, dS->one, P, p.p, dS->beta, S.nsites, R, s);
+    };
+
+    const double rms_target = P == OVL_F64 ? 1.0 : std::sqrt(12.0 * S.nsites) / 8.0;
+    int its = 0;
+    st->restarts = 0;
+    for (;;) {
+      // true residual r = b - D(m) x in FP64
+      S.dm(tmp64.p, x, OVL_F64, 0);
+      blas_axpby(OVL_F64, b, dS->one, OVL_F64, r64.p, nullptr, S.nsites, R, s);
+      blas_axpby(OVL_F64, tmp64.p, dS->mone, OVL_F64, r64.p, dS->one, S.nsites, R, s);
+      S.norm2(r64.p, OVL_F64, dS->rrn, dS);
+      OVL_HIP(hipMemcpyAsync(rn2.data(), dS->rrn, sizeof(double) * R, hipMemcpyDeviceToHost, s));
+      OVL_HIP(hipStreamSynchronize(s));
+      bool done = true;
+      for (int r = 0; r < R; ++r) {
+        const double res = bn2[r] > 0 ? std::sqrt(rn2[r] / bn2[r]) : 0.0;
+        OVL_REQUIRE(std::isfinite(res), OVL_E_NAN, "true residual is NaN or Inf");
+        st->true_residual[r] = res;
+        if (res > tol) done = false;
+      }
+      if (done) break;
+      if (its >= maxiter || st->restarts >= opt.max_restarts) {
+        rc = OVL_W_NOT_CONVERGED;
+        break;
+      }
+      ++st->restarts;
+
+      // inner system D e = r / scale, scale chosen so the rms element of the
+      // scaled residual is O(1/8) (keeps FP16 iterates away from under/overflow)
+      for (int r = 0; r < R; ++r) {
+        const double rn = std::sqrt(rn2[r]);
+        const bool act = st->true_residual[r] > tol && rn > 0.0;
+        const double sc = act ? rn / rms_target : 0.0;
+        hS.scale[2 * r] = sc;
+        hS.scale[2 * r + 1] = 0.0;
+        hS.iscale[2 * r] = act ? 1.0 / sc : 0.0;
+        hS.iscale[2 * r + 1] = 0.0;
+        hS.active[r] = act ? 1 : 0;
+        hS.bad[r] = 0;
+        // relative stop of the inner solve: what remains to reach tol (with
+        // margin) and, for a low-precision inner operator, inner_tol
+        double rel = act ? 0.5 * tol * std::sqrt(bn2[r]) / rn : 1.0;
+        if (P != OVL_F64) rel = std::max(rel, opt.inner_tol);
+        rel = std::min(rel, 1.0);
+        hS.target[r] = rel * rel * rms_target * rms_target;
+      }
+      OVL_HIP(hipMemcpyAsync(dS, &hS, sizeof(Scalars), hipMemcpyHostToDevice, s));
+      OVL_HIP(hipStreamSynchronize(s));
+      blas_axpby(OVL_F64, r64.p, dS->iscale, P, rin.p, nullptr, S.nsites, R, s);
+      blas_zero(e64.p, S.v64 * R, s);
+      S.norm2(rin.p, P, dS->rr, dS);
+      S.dm(p.p, rin.p, P, 1);
+
+      int inner = 0;
+      for (;;) {
+        int step;
+        if (opt.graph_chunk > 0 && inner > 0) {
+          if (!gexec) {
+            OVL_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+            const int64_t sa = st->sign_applies, da = st->dslash_applies;
+            for (int k = 0; k < opt.graph_chunk; ++k) body();
+            st->sign_applies = sa;  // captured, not executed: counted at replay
+            st->dslash_applies = da;
+            OVL_HIP(hipStreamEndCapture(s, &graph));
+            OVL_HIP(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+          }
+          OVL_HIP(hipGraphLaunch(gexec, s));
+          step = opt.graph_chunk;
+          st->sign_applies += static_cast<int64_t>(2) * R * step;
+          st->dslash_applies += static_cast<int64_t>(2) * R * step * S.per_sign_dw;
+        } else {
+          const int nrun = opt.graph_chunk > 0 ? 1 : check_every;
+          for (int k = 0; k < nrun; ++k) body();
+          step = nrun;
+        }
+        inner += step;
+        its += step;
+        OVL_HIP(hipMemcpyAsync(hS.active, dS->active, sizeof(hS.active) + sizeof(hS.bad), hipMemcpyDeviceToHost, s));
+        OVL_HIP(hipStreamSynchronize(s));
+        bool any = false;
+        for (int r = 0; r < R; ++r) {
+          if (hS.bad[r] == 2) throw Error(OVL_E_NAN, "NaN or Inf in a CG iterate");
+          if (hS.bad[r] == 1) throw Error(OVL_E_BREAKDOWN, "CG breakdown: p^dag p <= 0");
+          any = any || hS.active[r];
+        }
+        if (!any || its >= maxiter) break;
+      }
+      // x += scale * e
+      blas_axpby(OVL_F64, e64.p, dS->scale, OVL_F64, x, dS->one, S.nsites, R, s);
+    }
+    st->iterations = its;
+    OVL_HIP(hipStreamSynchronize(s));
+  } catch (...) {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipStreamSynchronize(s);
+    (void)hipEventDestroy(ev);
+    (void)hipStreamDestroy(s);
+    throw;
+  }
+  if (gexec) OVL_HIP(hipGraphExecDestroy(gexec));
+  if (graph) OVL_HIP(hipGraphDestroy(graph));
+  // the caller's stream continues after the solve
+  OVL_HIP(hipEventRecord(ev, s));
+  OVL_HIP(hipStreamWaitEvent(us, ev, 0));
+  OVL_HIP(hipStreamSynchronize(s));
+  OVL_HIP(hipEventDestroy(ev));
+  OVL_HIP(hipStreamDestroy(s));
+  st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  return rc;
+}
+
+}  // namespace ovl
+
+using namespace ovl;
+
+extern "C" {
+
+int ovl_cg_solve(void* x, const void* b, int nrhs, const ovl_gauge* u, double rho, double m, const ovl_sign* sign,
+                 const ovl_lowmodes* lowmodes, double tol, int maxiter, const ovl_solve_opts* opts,
+                 ovl_solve_stats* stats, ovl_stream_t s) {
+  return guard([&] {
+    OVL_REQUIRE(x && b && u && sign && stats, OVL_E_ARG, "null argument");
+    OVL_REQUIRE(nrhs >= 1 && nrhs <= OVL_MAX_RHS, OVL_E_ARG, "cg_solve: 1 <= nrhs <= 12");
+    OVL_REQUIRE(x != b, OVL_E_ALIAS, "x must not alias b");
+    OVL_REQUIRE(tol > 0.0 && maxiter >= 0, OVL_E_ARG, "need tol > 0 and maxiter >= 0");
+    OVL_REQUIRE(m > -2.0 * rho && m < 2.0 * rho, OVL_E_ARG, "need |m| < 2 rho");
+    if (lowmodes && lowmodes->ell == 0) lowmodes = nullptr;
+    if (opts) OVL_REQUIRE(opts->graph_chunk >= 0 && opts->graph_chunk <= 1000, OVL_E_ARG, "graph_chunk out of range");
+    *stats = ovl_solve_stats{};
+    return cg_solve(x, b, nrhs, u, rho, m, sign, lowmodes, tol, maxiter, opts, stats, static_cast<hipStream_t>(s));
+  });
+}
+
+int ovl_propagator(void* out, const void* x, const ovl_gauge* u, double rho, const ovl_sign* sign,
+                   const ovl_lowmodes* lowmodes, ovl_prec prec, int nrhs, ovl_stream_t s) {
+  return guard([&] {
+    OVL_REQUIRE(out && x && u && sign, OVL_E_ARG, "null argument");
+    check_prec(prec);
+    check_nrhs(nrhs);
+    OVL_REQUIRE(out != x, OVL_E_ALIAS, "output must not alias the input");
+    if (lowmodes && lowmodes->ell == 0) lowmodes = nullptr;
+    // (1 - D/2) x = x/2 - gamma5 sign(H_w) x / 2
+    overlap_combine(out, x, u, rho, 0.5, -0.5, sign, lowmodes, prec, nrhs, static_cast<hipStream_t>(s));
+    return OVL_OK;
+  });
+}
+
+}  // extern "C"

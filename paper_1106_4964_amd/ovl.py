@@ -69,6 +69,37 @@ SZ = ctypes.c_size_t
 ST = "stream"  # marker: a hipStream_t argument (None = torch's current stream)
 
 
+class SolveOpts(ctypes.Structure):
+    _fields_ = [
+        ("inner_prec", ctypes.c_int),
+        ("inner_tol", ctypes.c_double),
+        ("graph_chunk", ctypes.c_int),
+        ("check_every", ctypes.c_int),
+        ("max_restarts", ctypes.c_int),
+    ]
+
+
+class EigStats(ctypes.Structure):
+    _fields_ = [
+        ("iterations", ctypes.c_int),
+        ("hw_applies", ctypes.c_int64),
+        ("max_residual", ctypes.c_double),
+        ("seconds", ctypes.c_double),
+    ]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [
+        ("iterations", ctypes.c_int),
+        ("restarts", ctypes.c_int),
+        ("true_residual", ctypes.c_double * 12),
+        ("seconds", ctypes.c_double),
+        ("sign_applies", ctypes.c_int64),
+        ("dslash_applies", ctypes.c_int64),
+        ("fallback_used", ctypes.c_int),
+    ]
+
+
 def _sig(name, *args):
     fn = getattr(lib, name)
     fn.argtypes = list(args)
@@ -108,6 +139,12 @@ _SIGS = {
     "ovl_lowmodes_project": (P, P, P, P, I, I, ST),
     "ovl_sign_apply": (P, P, P, D, P, P, I, I, ST),
     "ovl_overlap_apply": (P, P, P, D, D, P, P, I, I, I, ST),
+    "ovl_cg_solve": (P, P, I, P, D, D, P, P, D, I, P, P, ST),
+    "ovl_propagator": (P, P, P, D, P, P, I, I, ST),
+    "ovl_counters": (P, P, I),
+    "ovl_hw_bound": (P, D, P, I, P, P, P, ST),
+    "ovl_hw_eigs": (P, D, I, I, P, P, D, D, I, I, P, ST),
+    "ovl_host_heev": (I, P, P, P),
 }
 
 EXPORTED = ["ovl_last_error", "ovl_version", "ovl_gauge_geom"] + list(_SIGS)
@@ -126,6 +163,8 @@ def _ptr(x):
         return x.ctypes.data
     if isinstance(x, ctypes.c_void_p):
         return x.value
+    if isinstance(x, ctypes.Structure):
+        return ctypes.addressof(x)
     return ctypes.cast(x, ctypes.c_void_p).value
 
 

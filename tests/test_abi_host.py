@@ -70,3 +70,25 @@ def test_null_and_alias_arguments_rejected_without_gpu():
     with pytest.raises(ovl.OvlError) as e:
         ovl.ovl_convert(g, 0x1000, ovl.OVL_F64, 0x1000, ovl.OVL_F32, 1, 0)
     assert e.value.name == "OVL_E_ALIAS"
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 40, 120])
+def test_host_heev_against_numpy(n):
+    """The host Jacobi eigensolver used by the GPU eigensolver, vs numpy.linalg.eigh."""
+    import numpy as np
+
+    from paper_1106_4964_amd import ovl
+
+    rng = np.random.default_rng(n)
+    a = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    h = a + a.conj().T
+    if n > 5:
+        h[0, 1] = h[1, 0] = 0.0  # a zero off-diagonal entry
+    A = np.asfortranarray(h).astype(np.complex128)
+    w = np.zeros(n)
+    V = np.zeros((n, n), dtype=np.complex128, order="F")
+    ovl.ovl_host_heev(n, A.ctypes.data, w, V.ctypes.data)
+    wn = np.linalg.eigvalsh(h)
+    assert np.max(np.abs(w - wn)) < 1e-12 * max(1.0, np.max(np.abs(wn)))
+    assert np.max(np.abs(h @ V - V * w)) < 1e-11 * max(1.0, np.max(np.abs(wn)))
+    assert np.max(np.abs(V.conj().T @ V - np.eye(n))) < 1e-13

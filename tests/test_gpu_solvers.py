@@ -1,0 +1,208 @@
+"""GPU spectral set-up (Lanczos bound, low modes) and CG, judged by the oracle."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import synth_inputs as si
+from oracle import dense, dirac, sign
+from oracle.lattice import Lattice
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+from paper_1106_4964_amd import ovl  # noqa: E402
+
+import gpu_util as gu  # noqa: E402
+
+RHO = 1.5
+
+
+@pytest.fixture(scope="module")
+def c1():
+    dims = (4, 4, 4, 4)
+    lat = Lattice(dims)
+    U = si.gauge_field(dims, 0.3, 1)
+    H = dense.dense_hw(lat, U, RHO)
+    w, v = dense.eig_sorted_by_magnitude(H)
+    return dict(dims=dims, lat=lat, U=U, H=H, w=w, v=v, lo=float(np.abs(w[0])), hi=float(np.max(np.abs(w))))
+
+
+def _bound(g, gauge, steps=60, seed=17):
+    v0 = gu.pack(g, si.gaussian_spinor(g.dims, seed), ovl.OVL_F64)
+    lam, tmin, tmax = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    ovl.ovl_hw_bound(gauge, RHO, v0, steps, ctypes.byref(lam), ctypes.byref(tmin), ctypes.byref(tmax), None)
+    return lam.value, tmin.value, tmax.value
+
+
+def _eigs(g, gauge, ell, m, lam_max, tol=1e-12, seed=5, max_iter=20, degree=30):
+    V0 = np.stack([si.gaussian_spinor(g.dims, seed + i) for i in range(m)])
+    V = gu.pack(g, V0, ovl.OVL_F64, m)
+    lam = np.zeros(ell)
+    st = ovl.EigStats()
+    rc = ovl.ovl_hw_eigs(gauge, RHO, ell, m, V, lam, lam_max, tol, max_iter, degree, ctypes.byref(st), None)
+    return rc, V, lam, st
+
+
+def test_lanczos_bound_c1(c1):
+    g = ovl.Geometry(c1["dims"])
+    gauge = gu.make_gauge(g, c1["U"])
+    lam, tmin, tmax = _bound(g, gauge)
+    assert lam >= c1["hi"]
+    assert lam <= c1["hi"] * 1.01
+    assert tmin >= -c1["hi"] - 1e-9 and tmax <= c1["hi"] + 1e-9
+
+
+def test_eigensolver_c1_against_dense(c1):
+    g = ovl.Geometry(c1["dims"])
+    gauge = gu.make_gauge(g, c1["U"])
+    ell, m = 10, 24
+    rc, V, lam, st = _eigs(g, gauge, ell, m, c1["hi"] * 1.0001)
+    assert rc == 0, (st.iterations, st.max_residual)
+    assert np.max(np.abs(lam - c1["w"][:ell])) < 1e-10 * c1["hi"]
+    Vh = gu.unpack(g, V, ovl.OVL_F64, m)[:ell]
+    for i in range(ell):
+        r = dirac.hw_apply(c1["lat"], c1["U"], Vh[i], RHO) - lam[i] * Vh[i]
+        assert np.linalg.norm(r) <= 1e-11 * c1["hi"]
+    G = Vh.reshape(ell, -1).conj() @ Vh.reshape(ell, -1).T
+    assert np.max(np.abs(G - np.eye(ell))) < 1e-13
+    print("eigs c1: iterations %d, H_w applies %d, max residual %.2e" % (st.iterations, st.hw_applies, st.max_residual))
+
+
+def test_eigensolver_8x8x8x8_residuals():
+    dims = (8, 8, 8, 8)
+    lat = Lattice(dims)
+    U = si.gauge_field(dims, 0.25, 2)
+    g = ovl.Geometry(dims)
+    gauge = gu.make_gauge(g, U)
+    lam_max, _, _ = _bound(g, gauge)
+    ell, m = 12, 32
+    rc, V, lam, st = _eigs(g, gauge, ell, m, lam_max)
+    assert rc == 0, (st.iterations, st.max_residual)
+    assert np.all(np.diff(np.abs(lam)) >= -1e-12)
+    Vh = gu.unpack(g, V, ovl.OVL_F64, m)[:ell]
+    for i in range(ell):
+        r = dirac.hw_apply(lat, U, Vh[i], RHO) - lam[i] * Vh[i]
+        assert np.linalg.norm(r) <= 2e-12 * lam_max
+    G = Vh.reshape(ell, -1).conj() @ Vh.reshape(ell, -1).T
+    assert np.max(np.abs(G - np.eye(ell))) < 1e-13
+
+
+def _solve(g, gauge, s, lm, b, m, prec=ovl.OVL_F64, inner_tol=0.0, graph=0, maxiter=5000, tol=1e-10):
+    R = b.shape[0]
+    bd = gu.pack(g, b, ovl.OVL_F64, R)
+    x = gu.pack(g, np.zeros_like(b), ovl.OVL_F64, R)
+    opts = ovl.SolveOpts(prec, inner_tol, graph, 1, 50)
+    st = ovl.SolveStats()
+    rc = ovl.ovl_cg_solve(x, bd, R, gauge, RHO, m, s, lm, tol, maxiter, opts, st, None)
+    return rc, gu.unpack(g, x, ovl.OVL_F64, R), st
+
+
+def test_cg_f64_matches_dense_lu():
+    dims = (2, 2, 2, 2)
+    lat = Lattice(dims)
+    U = si.gauge_field(dims, 0.3, 2)
+    H = dense.dense_hw(lat, U, RHO)
+    lo, hi = dense.spectrum_bounds(H)
+    g = ovl.Geometry(dims)
+    gauge = gu.make_gauge(g, U)
+    n = 60
+    s = ovl.Sign(lo, hi, n=n)
+    so = sign.make_sign(lo, hi, n)
+    b = si.point_source(dims, 1, 2)[None]
+    rc, x, st = _solve(g, gauge, s, None, b, 0.01)
+    assert rc == 0
+    assert st.true_residual[0] <= 1e-10
+    Dm = lambda v: sign.overlap_apply(lat, U, v, RHO, 0.01, so)  # noqa: E731
+    M = dense.dense_operator(lat, Dm)
+    xd = np.linalg.solve(M, b[0].reshape(-1))
+    kappa = np.linalg.cond(M)
+    assert np.linalg.norm(x.reshape(-1) - xd) <= 2 * kappa * 1e-10 * np.linalg.norm(xd)
+    # the oracle's own FP64 operator judges the residual
+    r = b[0] - Dm(x.reshape(g.N, 4, 3))
+    assert np.linalg.norm(r) / np.linalg.norm(b[0]) <= 1.05e-10
+
+
+@pytest.fixture(scope="module")
+def c1_lowmodes(c1):
+    ell = 10
+    V = np.ascontiguousarray(c1["v"][:, :ell].T).reshape(ell, c1["lat"].N, 4, 3)
+    lam = c1["w"][:ell].copy()
+    return V, lam
+
+
+@pytest.mark.parametrize("prec,graph", [(ovl.OVL_F64, 0), (ovl.OVL_F32, 0), (ovl.OVL_F16, 4), (ovl.OVL_BF16, 4)])
+def test_cg_12_point_sources_with_lowmodes(c1, c1_lowmodes, prec, graph):
+    """12 point sources at 4^4, low modes projected, inner precision `prec`,
+    FP64 true residual <= 1e-10 judged by the oracle's own operator."""
+    V, lam = c1_lowmodes
+    g = ovl.Geometry(c1["dims"])
+    reprs = [] if prec == ovl.OVL_F64 else [(prec, 1)]
+    gauge = gu.make_gauge(g, c1["U"], reprs)
+    lm = ovl.LowModes(g, gu.pack(g, V, ovl.OVL_F64, len(V)), lam)
+    lo = abs(lam[-1])
+    s = ovl.Sign(lo, c1["hi"], delta=1e-12)
+    so = sign.SignApprox(lam_max=c1["hi"], eps=s.eps, coeffs=s.coeffs())  # same coefficients as data
+    b = si.point_sources(c1["dims"])
+    inner_tol = {ovl.OVL_F64: 0.0, ovl.OVL_F32: 1e-5, ovl.OVL_F16: 1e-2, ovl.OVL_BF16: 3e-2}[prec]
+    rc, x, st = _solve(g, gauge, s, lm, b, 0.01, prec, inner_tol, graph)
+    assert rc == 0, list(st.true_residual)
+    print("cg prec %d: iterations %d restarts %d seconds %.2f sign applies %d" %
+          (prec, st.iterations, st.restarts, st.seconds, st.sign_applies))
+    for r in (0, 4, 11):
+        res = b[r] - sign.overlap_apply(c1["lat"], c1["U"], x[r], RHO, 0.01, so, V, lam)
+        assert np.linalg.norm(res) / np.linalg.norm(b[r]) <= 1.05e-10
+        assert st.true_residual[r] <= 1e-10
+
+
+def test_cg_batch_equals_single(c1, c1_lowmodes):
+    V, lam = c1_lowmodes
+    g = ovl.Geometry(c1["dims"])
+    gauge = gu.make_gauge(g, c1["U"])
+    lm = ovl.LowModes(g, gu.pack(g, V, ovl.OVL_F64, len(V)), lam)
+    s = ovl.Sign(abs(lam[-1]), c1["hi"], n=80)
+    b = si.point_sources(c1["dims"])[[0, 7, 11]]
+    _, xb, _ = _solve(g, gauge, s, lm, b, 0.05)
+    for k in range(3):
+        _, xs, _ = _solve(g, gauge, s, lm, b[k:k + 1], 0.05)
+        assert np.max(np.abs(xs - xb[k])) <= 1e-12 * np.max(np.abs(xb[k]))
+
+
+def test_cg_maxiter_and_nan(c1):
+    g = ovl.Geometry(c1["dims"])
+    gauge = gu.make_gauge(g, c1["U"])
+    s = ovl.Sign(c1["lo"], c1["hi"], n=40)
+    b = si.point_sources(c1["dims"])[:1]
+    rc, x, st = _solve(g, gauge, s, None, b, 0.01, maxiter=3)
+    assert rc == ovl.OVL_W_NOT_CONVERGED and st.iterations == 3 and st.true_residual[0] > 1e-10
+    bad = b.copy()
+    bad[0, 3, 1, 2] = np.nan
+    with pytest.raises(ovl.OvlError) as e:
+        _solve(g, gauge, s, None, bad, 0.01)
+    assert e.value.name == "OVL_E_NAN"
+
+
+def test_propagator(c1):
+    g = ovl.Geometry(c1["dims"])
+    gauge = gu.make_gauge(g, c1["U"])
+    s = ovl.Sign(c1["lo"], c1["hi"], n=60)
+    so = sign.make_sign(c1["lo"], c1["hi"], 60)
+    x = si.gaussian_spinor(c1["dims"], 9)
+    xd = gu.pack(g, x, ovl.OVL_F64)
+    out = gu.empty_field(g, ovl.OVL_F64)
+    ovl.ovl_propagator(out, xd, gauge, RHO, s, None, ovl.OVL_F64, 1, None)
+    got = gu.unpack(g, out, ovl.OVL_F64)
+    want = x - 0.5 * sign.massless_overlap(c1["lat"], c1["U"], x, RHO, so)
+    assert gu.max_rel_err(got, want) < 1e-12
+
+
+def test_sign_dslash_count_is_2n_plus_1(c1):
+    g = ovl.Geometry(c1["dims"])
+    gauge = gu.make_gauge(g, c1["U"])
+    s = ovl.Sign(c1["lo"], c1["hi"], n=37)
+    inp = gu.pack(g, si.gaussian_spinor(c1["dims"], 1), ovl.OVL_F64)
+    out = gu.empty_field(g, ovl.OVL_F64)
+    ovl.ovl_counters(None, None, 1)
+    ovl.ovl_sign_apply(out, inp, gauge, RHO, s, None, ovl.OVL_F64, 1, None)
+    launches, vectors = ctypes.c_int64(), ctypes.c_int64()
+    ovl.ovl_counters(ctypes.byref(launches), ctypes.byref(vectors), 0)
+    assert vectors.value == 2 * 37 + 1
