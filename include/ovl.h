@@ -230,11 +230,14 @@ int ovl_overlap_apply(void* out, const void* in, const ovl_gauge* u, double rho,
  *   solution x of D(m) x = b.
  */
 typedef struct {
-  ovl_prec inner_prec; /* precision of the inner CG                       */
+  ovl_prec inner_prec; /* precision of the inner solve                    */
   double inner_tol;    /* low-precision inner solve: relative reduction   */
-  int graph_chunk;     /* > 0: inner iterations per captured HIP graph     */
+  int graph_chunk;     /* > 0: inner CG iterations per captured HIP graph  */
   int check_every;     /* without graphs: iterations between host checks  */
   int max_restarts;    /* FP64 defect-correction cycles                   */
+  void* harvest_x;     /* CG only: FP32 buffers that receive exact pairs  */
+  void* harvest_b;     /*   (x, b = D(m) x) from the CG matvecs; NULL=off */
+  int harvest_cap;     /*   capacity of each buffer, in spinors           */
 } ovl_solve_opts;
 
 typedef struct {
@@ -245,11 +248,25 @@ typedef struct {
   int64_t sign_applies;                 /* vector applications of sign(H_w)  */
   int64_t dslash_applies;               /* vector applications of D_w        */
   int fallback_used;                    /* FGCR only: CG finished the solve  */
+  int harvested;                        /* pairs written to the harvest bufs */
 } ovl_solve_stats;
 
 int ovl_cg_solve(void* x, const void* b, int nrhs, const ovl_gauge* u, double rho, double m, const ovl_sign* sign,
                  const ovl_lowmodes* lowmodes, double tol, int maxiter, const ovl_solve_opts* opts,
                  ovl_solve_stats* stats, ovl_stream_t s);
+/* ovl_fgcr_solve: solves D(m) x = b (nrhs <= 12) by flexible GCR with the
+ *   learned network M as right preconditioner (z = M r, w = D(m) z, w
+ *   orthogonalised against the earlier w's of the cycle, restart length
+ *   `restart` <= 32), inside the same FP64 defect-correction loop as
+ *   ovl_cg_solve; D(m) inside the cycle runs at opts->inner_prec, M in FP32
+ *   (needs the FP32 link representation).  M = NULL gives plain GCR.  If a
+ *   cycle reduces the residual by less than a factor 0.9, or an iterate is
+ *   not finite, the solve is finished by ovl_cg_solve from the current x and
+ *   stats->fallback_used is set.  Bases: 2*restart*nrhs FP64 spinors.
+ */
+int ovl_fgcr_solve(void* x, const void* b, int nrhs, const ovl_gauge* u, double rho, double m, const ovl_sign* sign,
+                   const ovl_lowmodes* lowmodes, const ovl_net* M, int restart, double tol, int maxiter,
+                   const ovl_solve_opts* opts, ovl_solve_stats* stats, ovl_stream_t s);
 int ovl_propagator(void* out, const void* x, const ovl_gauge* u, double rho, const ovl_sign* sign,
                    const ovl_lowmodes* lowmodes, ovl_prec prec, int nrhs, ovl_stream_t s);
 
@@ -289,6 +306,39 @@ int ovl_hw_eigs(const ovl_gauge* u, double rho, int ell, int m, void* V, double*
  * eigensolver uses for its Gram and Rayleigh-Ritz matrices.
  */
 int ovl_host_heev(int n, const double* A, double* w, double* V);
+
+/* --------------------------------------------------- learned preconditioner
+ * A 2-layer gauge-equivariant parallel-transport convolution network
+ * 1 -> hidden -> 1 channels (not part of the paper): each layer is
+ *   out[a](x) = sum_b sum_k W[k][a][b] (T_k in[b])(x), k = 0..8,
+ * T_0 = 1, T_{+mu} phi(x) = U_mu(x) phi(x+mu), T_{-mu} phi(x) =
+ * U_mu(x-mu)^dag phi(x-mu) (the transporters of eq. 2 without spin
+ * projector), W[k][a][b] a complex 4x4 spin matrix.  Weights: complex128
+ * host arrays, layout [k][a][b][4][4] (layer 1: 9 x hidden x 1, layer 2:
+ * 9 x 1 x hidden).  Activations: FP32 spinors; links: the FP32
+ * representation of the gauge field.
+ * ovl_ptc_layer_forward: one layer, cin/cout channels (vectors back to back).
+ * ovl_ptc_layer_backward: gin = layer^dag gout (if gin != NULL) and the
+ *   weight gradient gW[k][a][b] = sum_x sum_colour gout[a](x) (T_k in[b](x))^dag
+ *   (host complex128, if gW != NULL), for real losses with the convention
+ *   grad z = dL/dRe z + i dL/dIm z.  cin*cout <= 4.
+ * ovl_net_train: `epochs` passes of mini-batch Adam (betas 0.9, 0.999) on
+ *   the loss mean_i ||M b_i - x_i||^2 / ||x_i||^2 over npairs FP32 pairs
+ *   (B, X: device batches); order: epochs*npairs caller-drawn indices into
+ *   the pairs; loss_history[epoch] (may be NULL) receives the mean loss.
+ * ovl_net_apply: out = M in for one FP32 spinor.
+ */
+int ovl_net_create(const ovl_geom* g, int hidden, ovl_net** out);
+int ovl_net_destroy(ovl_net* n);
+int ovl_net_set_weights(ovl_net* n, const double* w1, const double* w2);
+int ovl_net_get_weights(const ovl_net* n, double* w1, double* w2);
+int ovl_ptc_layer_forward(const ovl_gauge* u, const void* in, int cin, void* out, int cout, const double* W,
+                          ovl_stream_t s);
+int ovl_ptc_layer_backward(const ovl_gauge* u, const void* in, int cin, const void* gout, int cout, const double* W,
+                           void* gin, double* gW, ovl_stream_t s);
+int ovl_net_train(ovl_net* n, const ovl_gauge* u, const void* B, const void* X, int npairs, int epochs, int batch,
+                  double lr, const int32_t* order, double* loss_history, ovl_stream_t s);
+int ovl_net_apply(const ovl_net* n, const ovl_gauge* u, const void* in, void* out, ovl_stream_t s);
 
 /* ovl_counters: stencil launches and vector applications of D_w issued from
  * the host since the last reset (graph replays are not seen here).

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 #include <hip/hip_fp16.h>
 
+#include <complex>
 #include <cstdint>
 #include <cstring>
 #include <map>
@@ -111,15 +112,11 @@ struct bf16_t {
 };
 
 __host__ __device__ inline float bf16_to_float(uint16_t b) {
-  uint32_t u = static_cast<uint32_t>(b) << 16;
-  float f;
-  memcpy(&f, &u, 4);
-  return f;
+  return __builtin_bit_cast(float, static_cast<uint32_t>(b) << 16);
 }
 // Round to nearest even; NaN stays a (quiet) NaN.
 __host__ __device__ inline uint16_t float_to_bf16(float f) {
-  uint32_t u;
-  memcpy(&u, &f, 4);
+  uint32_t u = __builtin_bit_cast(uint32_t, f);
   if ((u & 0x7fffffffu) > 0x7f800000u) return static_cast<uint16_t>((u >> 16) | 0x40);
   u += 0x7fffu + ((u >> 16) & 1u);
   return static_cast<uint16_t>(u >> 16);
@@ -436,6 +433,13 @@ struct ovl_lowmodes {
   const void* V;  // borrowed: ell FP64 spinors
   std::vector<double> lambda;
   double* dev_sign = nullptr;  // sign(lambda_i) on the device
+};
+
+struct ovl_net {
+  ovl_geom geom;
+  int hidden;
+  // host FP64 weights, layout [k][a][b][s][t] complex
+  std::vector<std::complex<double>> w1, w2;  // 9 x hidden x 1 x 16, 9 x 1 x hidden x 16
 };
 
 namespace ovl {

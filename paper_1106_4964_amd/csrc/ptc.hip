@@ -22,13 +22,6 @@
 
 #include "ops.h"
 
-struct ovl_net {
-  ovl_geom geom;
-  int hidden;
-  // host FP64 weights, layout [k][a][b][s][t] complex
-  std::vector<std::complex<double>> w1, w2;  // 9 x hidden x 1 x 16, 9 x 1 x hidden x 16
-};
-
 namespace ovl {
 namespace {
 
@@ -174,7 +167,8 @@ __global__ __launch_bounds__(256) void ptc_wgrad_kernel(Geo g, const void* links
   }
 }
 
-__global__ void wgrad_reduce_kernel(int nout, int G, const double2* partial, double2* out) {
+// out[k][i] (+)= sum_b partial[k][b][i], blocks in order.
+__global__ void wgrad_reduce_kernel(int nout, int G, const double2* partial, double2* out, int accumulate) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int k = blockIdx.y;
   if (i >= nout) return;
@@ -184,7 +178,22 @@ __global__ void wgrad_reduce_kernel(int nout, int G, const double2* partial, dou
     re += v.x;
     im += v.y;
   }
-  out[static_cast<size_t>(k) * nout + i] = make_double2(re, im);
+  double2* o = out + static_cast<size_t>(k) * nout + i;
+  if (accumulate) {
+    re += o->x;
+    im += o->y;
+  }
+  *o = make_double2(re, im);
+}
+
+// loss[0] += d2[0] / x2[0];  gscale = (2 / x2[0], 0): the gradient of
+// ||out - x||^2 / ||x||^2 with respect to out is gscale * (out - x).
+__global__ void pair_loss_kernel(const double* d2, const double* x2, double* loss, double* gscale) {
+  if (threadIdx.x == 0) {
+    loss[0] += d2[0] / x2[0];
+    gscale[0] = 2.0 / x2[0];
+    gscale[1] = 0.0;
+  }
 }
 
 constexpr int WG_BLOCKS = 256;
@@ -231,7 +240,7 @@ struct Layer {
                          static_cast<char*>(out), vstride, cin, cout, W);
     OVL_HIP(hipGetLastError());
   }
-  void wgrad(const void* in, const void* gout, int cin, int cout, double2* out) const {
+  void wgrad(const void* in, const void* gout, int cin, int cout, double2* out, int accumulate = 0) const {
     const Geo& g = u->geom.geo;
     const int nout = cin * cout * 16;
     WsBuf part(static_cast<size_t>(NPATH) * WG_BLOCKS * nout * sizeof(double2), s);
@@ -244,10 +253,12 @@ struct Layer {
                          static_cast<const char*>(gout), vstride, cin, cout, static_cast<double2*>(part.p));
     OVL_HIP(hipGetLastError());
     hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((nout + 255) / 256, NPATH), dim3(256), 0, s, nout, WG_BLOCKS,
-                       static_cast<const double2*>(part.p), out);
+                       static_cast<const double2*>(part.p), out, accumulate);
     OVL_HIP(hipGetLastError());
   }
 };
+
+size_t g_nsites(const ovl_gauge* u) { return static_cast<size_t>(u->geom.N); }
 
 Layer make_layer(const ovl_gauge* u, hipStream_t s) {
   Layer L{u, nullptr, 0, s, spinor_vec_bytes(&u->geom, OVL_F32)};
@@ -363,11 +374,98 @@ int ovl_ptc_layer_backward(const ovl_gauge* u, const void* in, int cin, const vo
   });
 }
 
+int ovl_net_train(ovl_net* n, const ovl_gauge* u, const void* B, const void* X, int npairs, int epochs, int batch,
+                  double lr, const int32_t* order, double* loss_history, ovl_stream_t st) {
+  return guard([&] {
+    OVL_REQUIRE(n && u && B && X && order, OVL_E_ARG, "null argument");
+    OVL_REQUIRE(npairs >= 1 && epochs >= 1 && batch >= 1 && lr > 0.0, OVL_E_ARG, "bad training parameter");
+    hipStream_t s = static_cast<hipStream_t>(st);
+    Layer L = make_layer(u, s);
+    const int C = n->hidden;
+    const size_t vs = L.vstride;
+    const size_t nw = n->w1.size();  // = n->w2.size()
+    WsBuf hid(vs * C, s), out(vs, s), gout(vs, s), gh(vs * C, s);
+    WsBuf dw1(nw * sizeof(float2), s), dw2(nw * sizeof(float2), s), dw2a(nw * sizeof(float2), s);
+    WsBuf g1(nw * sizeof(double2), s), g2(nw * sizeof(double2), s);
+    WsBuf sc(8 * sizeof(double), s);
+    double* dsc = static_cast<double*>(sc.p);  // [0..1] norm tmp, [2] x2, [3] d2, [4] loss, [6..7] gscale
+    const double one_m1[4] = {1.0, 0.0, -1.0, 0.0};
+    WsBuf cst(4 * sizeof(double), s);
+    OVL_HIP(hipMemcpyAsync(cst.p, one_m1, sizeof(one_m1), hipMemcpyHostToDevice, s));
+    const double* d_one = static_cast<const double*>(cst.p);
+    const double* d_m1 = d_one + 2;
+    // Adam state over the real and imaginary parts of every weight
+    std::vector<double> m1(4 * nw, 0.0), v1(4 * nw, 0.0);
+    const double b1 = 0.9, b2 = 0.999, eps = 1e-8;
+    int tstep = 0;
+    std::vector<double2> hg(nw);
+    const size_t n16 = vs / 16;
+    auto norm2_into = [&](const void* x, double* dst) {
+      blas_norm2(OVL_F32, n16, x, 1, vs, dsc, s);
+      OVL_HIP(hipMemcpyAsync(dst, dsc, sizeof(double), hipMemcpyDeviceToDevice, s));
+    };
+    for (int ep = 0; ep < epochs; ++ep) {
+      double zero = 0.0;
+      OVL_HIP(hipMemcpyAsync(dsc + 4, &zero, sizeof(double), hipMemcpyHostToDevice, s));
+      for (int b0 = 0; b0 < npairs; b0 += batch) {
+        const int nb = std::min(batch, npairs - b0);
+        upload(n->w1, static_cast<float2*>(dw1.p), s);
+        upload(n->w2, static_cast<float2*>(dw2.p), s);
+        upload(adjoint_weights(n->w2, C, 1), static_cast<float2*>(dw2a.p), s);
+        blas_zero(g1.p, nw * sizeof(double2), s);
+        blas_zero(g2.p, nw * sizeof(double2), s);
+        for (int q = 0; q < nb; ++q) {
+          const int idx = order[static_cast<size_t>(ep) * npairs + b0 + q];
+          OVL_REQUIRE(idx >= 0 && idx < npairs, OVL_E_ARG, "training order index out of range");
+          const char* bb = static_cast<const char*>(B) + static_cast<size_t>(idx) * vs;
+          const char* xx = static_cast<const char*>(X) + static_cast<size_t>(idx) * vs;
+          L.forward(bb, hid.p, 1, C, static_cast<const float2*>(dw1.p));
+          L.forward(hid.p, out.p, C, 1, static_cast<const float2*>(dw2.p));
+          // diff = out - x (into gout), loss and gradient scale
+          blas_axpby(OVL_F32, xx, d_m1, OVL_F32, out.p, d_one, g_nsites(u), 1, s);
+          norm2_into(xx, dsc + 2);
+          norm2_into(out.p, dsc + 3);
+          hipLaunchKernelGGL(pair_loss_kernel, dim3(1), dim3(64), 0, s, dsc + 3, dsc + 2, dsc + 4, dsc + 6);
+          blas_axpby(OVL_F32, out.p, dsc + 6, OVL_F32, gout.p, nullptr, g_nsites(u), 1, s);
+          // layer 2: weight gradient and input gradient; layer 1: weight gradient
+          L.wgrad(hid.p, gout.p, C, 1, static_cast<double2*>(g2.p), 1);
+          L.forward(gout.p, gh.p, 1, C, static_cast<const float2*>(dw2a.p));
+          L.wgrad(bb, gh.p, 1, C, static_cast<double2*>(g1.p), 1);
+        }
+        // Adam step on the mean gradient of the batch
+        ++tstep;
+        for (int layer = 0; layer < 2; ++layer) {
+          OVL_HIP(hipMemcpyAsync(hg.data(), layer == 0 ? g1.p : g2.p, nw * sizeof(double2), hipMemcpyDeviceToHost, s));
+          OVL_HIP(hipStreamSynchronize(s));
+          std::vector<zc>& W = layer == 0 ? n->w1 : n->w2;
+          for (size_t i = 0; i < nw; ++i) {
+            const double gr[2] = {hg[i].x / nb, hg[i].y / nb};
+            double wv[2] = {W[i].real(), W[i].imag()};
+            for (int c = 0; c < 2; ++c) {
+              const size_t k = (layer * nw + i) * 2 + c;
+              m1[k] = b1 * m1[k] + (1 - b1) * gr[c];
+              v1[k] = b2 * v1[k] + (1 - b2) * gr[c] * gr[c];
+              const double mh = m1[k] / (1 - std::pow(b1, tstep)), vh = v1[k] / (1 - std::pow(b2, tstep));
+              wv[c] -= lr * mh / (std::sqrt(vh) + eps);
+            }
+            W[i] = zc(wv[0], wv[1]);
+          }
+        }
+      }
+      double loss = 0.0;
+      OVL_HIP(hipMemcpyAsync(&loss, dsc + 4, sizeof(double), hipMemcpyDeviceToHost, s));
+      OVL_HIP(hipStreamSynchronize(s));
+      OVL_REQUIRE(std::isfinite(loss), OVL_E_NAN, "training loss is NaN or Inf");
+      if (loss_history) loss_history[ep] = loss / npairs;
+    }
+    return OVL_OK;
+  });
+}
+
 int ovl_net_apply(const ovl_net* n, const ovl_gauge* u, const void* in, void* out, ovl_stream_t st) {
   return guard([&] {
     OVL_REQUIRE(n && u && in && out, OVL_E_ARG, "null argument");
     OVL_REQUIRE(in != out, OVL_E_ALIAS, "output must not alias the input");
-    OVL_REQUIRE(n->geom.N == u->geom.N || true, OVL_E_ARG, "");
     net_apply(n, u, in, out, static_cast<hipStream_t>(st));
     return OVL_OK;
   });

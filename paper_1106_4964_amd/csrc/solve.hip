@@ -161,6 +161,7 @@ int cg_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, doub
     WsBuf sbuf(sizeof(Scalars), s);
     Scalars* dS = static_cast<Scalars*>(sbuf.p);
     Scalars hS{};
+    bool capturing = false;
     for (int r = 0; r < R; ++r) {
       hS.one[2 * r] = 1.0;
       hS.mone[2 * r] = -1.0;
@@ -178,12 +179,27 @@ int cg_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, doub
       OVL_REQUIRE(std::isfinite(bn2[r]), OVL_E_NAN, "right-hand side contains NaN or Inf");
     }
 
+    // exact pairs (x = p_r, b = D(m) p_r) for training, outside graphs only
+    const bool harvest = opt.harvest_x && opt.harvest_b && opt.harvest_cap > 0;
+    const size_t v32 = spinor_vec_bytes(&u->geom, OVL_F32);
+    auto harvest_pairs = [&]() {
+      for (int r = 0; r < R && st->harvested < opt.harvest_cap; ++r) {
+        if (!hS.active[r]) continue;
+        blas_convert(P, static_cast<char*>(p.p) + r * S.vP, OVL_F32,
+                     static_cast<char*>(opt.harvest_x) + st->harvested * v32, S.nsites, 1, s);
+        blas_convert(P, static_cast<char*>(q.p) + r * S.vP, OVL_F32,
+                     static_cast<char*>(opt.harvest_b) + st->harvested * v32, S.nsites, 1, s);
+        ++st->harvested;
+      }
+    };
+
     // inner-iteration body; records nothing but kernel launches
     auto body = [&]() {
       S.norm2(p.p, P, dS->pp, dS);
       hipLaunchKernelGGL(alpha_kernel, dim3(1), dim3(64), 0, s, R, dS);
       blas_axpby(P, p.p, dS->alpha, OVL_F64, e64.p, dS->one, S.nsites, R, s);
       S.dm(q.p, p.p, P, 0);
+      if (harvest && !capturing) harvest_pairs();
       blas_axpby(P, q.p, dS->malpha, P, rin.p, dS->one, S.nsites, R, s);
       S.norm2(rin.p, P, dS->rrn, dS);
       hipLaunchKernelGGL(beta_kernel, dim3(1), dim3(64), 0, s, R, dS);
@@ -245,14 +261,16 @@ int cg_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, doub
       int inner = 0;
       for (;;) {
         int step;
-        if (opt.graph_chunk > 0 && inner > 0) {
+        if (opt.graph_chunk > 0 && inner > 0 && !harvest) {
           if (!gexec) {
+            capturing = true;
             OVL_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
             const int64_t sa = st->sign_applies, da = st->dslash_applies;
             for (int k = 0; k < opt.graph_chunk; ++k) body();
             st->sign_applies = sa;  // captured, not executed: counted at replay
             st->dslash_applies = da;
             OVL_HIP(hipStreamEndCapture(s, &graph));
+            capturing = false;
             OVL_HIP(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
           }
           OVL_HIP(hipGraphLaunch(gexec, s));
@@ -260,7 +278,7 @@ int cg_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, doub
           st->sign_applies += static_cast<int64_t>(2) * R * step;
           st->dslash_applies += static_cast<int64_t>(2) * R * step * S.per_sign_dw;
         } else {
-          const int nrun = opt.graph_chunk > 0 ? 1 : check_every;
+          const int nrun = (opt.graph_chunk > 0 || harvest) ? 1 : check_every;
           for (int k = 0; k < nrun; ++k) body();
           step = nrun;
         }
@@ -301,6 +319,244 @@ int cg_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, doub
   return rc;
 }
 
+
+// ------------------------------------------------------------------- FGCR
+// Flexible GCR with a right preconditioner M (the learned network, FP32) in
+// the FP64 defect-correction loop.  Each rhs keeps its own bases W (the
+// orthonormalised D(m) z) and Z (the matching search directions) in FP64;
+// the D(m) applications of a cycle run as one batch at the inner precision.
+int fgcr_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, double m, const ovl_sign* sg,
+               const ovl_lowmodes* lm, const ovl_net* net, int restart, double tol, int maxiter,
+               const ovl_solve_opts* o, ovl_solve_stats* st, hipStream_t us) {
+  const auto t_start = std::chrono::steady_clock::now();
+  const int P = o ? o->inner_prec : OVL_F64;
+  const double inner_tol = o ? o->inner_tol : 0.0;
+  const int max_restarts = o ? o->max_restarts : 50;
+  check_prec(P);
+  int recon = 0;
+  (void)gauge_links(u, P, &recon);
+  if (net) (void)gauge_links(u, OVL_F32, &recon);
+  const ovl_geom* g = &u->geom;
+  const size_t N = static_cast<size_t>(g->N);
+  const size_t v64 = spinor_vec_bytes(g, OVL_F64), vP = spinor_vec_bytes(g, P), v32 = spinor_vec_bytes(g, OVL_F32);
+  const int64_t per_sign_dw = 2 * (static_cast<int64_t>(sg->c.size()) - 1) + 1;
+
+  hipStream_t s;
+  OVL_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  hipEvent_t ev;
+  OVL_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  OVL_HIP(hipEventRecord(ev, us));
+  OVL_HIP(hipStreamWaitEvent(s, ev, 0));
+  int rc = OVL_OK;
+  bool fallback = false;
+  try {
+    WsBuf r64(v64 * R, s), tmp64(v64 * R, s), e64(v64 * R, s), rin(v64 * R, s);
+    WsBuf zP(vP * R, s), wP(vP * R, s), w64(v64 * R, s), z64(v64 * R, s);
+    WsBuf r32(net ? v32 * R : 16, s), z32(net ? v32 * R : 16, s);
+    WsBuf Wb(v64 * R * restart, s), Zb(v64 * R * restart, s);
+    WsBuf sc(sizeof(double) * 4 * OVL_MAX_RHS, s), cb(sizeof(double2) * restart, s);
+    double* dsc = static_cast<double*>(sc.p);
+    std::vector<double> bn2(R), rn2(R), h(4 * OVL_MAX_RHS);
+    auto dev_scalars = [&](const std::vector<double>& v) {  // complex pairs -> dsc
+      OVL_HIP(hipMemcpyAsync(dsc, v.data(), sizeof(double) * v.size(), hipMemcpyHostToDevice, s));
+      OVL_HIP(hipStreamSynchronize(s));
+    };
+    auto norms = [&](const void* xx, int nr, size_t vs, int prec, std::vector<double>& out) {
+      blas_norm2(prec, vs / 16, xx, nr, vs, dsc, s);
+      OVL_HIP(hipMemcpyAsync(h.data(), dsc, sizeof(double) * 2 * nr, hipMemcpyDeviceToHost, s));
+      OVL_HIP(hipStreamSynchronize(s));
+      out.resize(nr);
+      for (int r = 0; r < nr; ++r) out[r] = h[2 * r];
+    };
+    auto dm = [&](void* out, const void* in, int prec) {
+      overlap_apply(out, in, u, rho, m, sg, lm, 1, prec, R, s);
+      st->sign_applies += R;
+      st->dslash_applies += R * per_sign_dw;
+    };
+    auto vec = [&](void* base, size_t vs, int i) { return static_cast<char*>(base) + static_cast<size_t>(i) * vs; };
+    // y_r += a x_r for one rhs (host scalar)
+    auto axpy1 = [&](const void* xx, void* yy, std::complex<double> a) {
+      std::vector<double> c = {a.real(), a.imag(), 1.0, 0.0};
+      dev_scalars(c);
+      blas_axpby(OVL_F64, xx, dsc, OVL_F64, yy, dsc + 2, N, 1, s);
+    };
+    auto dot1 = [&](const void* xx, const void* yy) {
+      blas_dot(OVL_F64, v64 / 16, xx, yy, 1, v64, dsc, s);
+      OVL_HIP(hipMemcpyAsync(h.data(), dsc, sizeof(double) * 2, hipMemcpyDeviceToHost, s));
+      OVL_HIP(hipStreamSynchronize(s));
+      return std::complex<double>(h[0], h[1]);
+    };
+
+    norms(b, R, v64, OVL_F64, bn2);
+    for (int r = 0; r < R; ++r) OVL_REQUIRE(std::isfinite(bn2[r]), OVL_E_NAN, "right-hand side contains NaN or Inf");
+    const double rms_target = P == OVL_F64 ? 1.0 : std::sqrt(12.0 * N) / 8.0;
+    int its = 0;
+    st->restarts = 0;
+    std::vector<double> ones(2 * OVL_MAX_RHS, 0.0), mones(2 * OVL_MAX_RHS, 0.0);
+    for (int r = 0; r < R; ++r) {
+      ones[2 * r] = 1.0;
+      mones[2 * r] = -1.0;
+    }
+    for (;;) {
+      dm(tmp64.p, x, OVL_F64);
+      std::vector<double> c(4 * OVL_MAX_RHS, 0.0);
+      for (int r = 0; r < R; ++r) {
+        c[2 * r] = 1.0;
+        c[2 * OVL_MAX_RHS + 2 * r] = -1.0;
+      }
+      dev_scalars(c);
+      blas_axpby(OVL_F64, b, dsc, OVL_F64, r64.p, nullptr, N, R, s);
+      blas_axpby(OVL_F64, tmp64.p, dsc + 2 * OVL_MAX_RHS, OVL_F64, r64.p, dsc, N, R, s);
+      norms(r64.p, R, v64, OVL_F64, rn2);
+      bool done = true;
+      std::vector<int> active(R);
+      for (int r = 0; r < R; ++r) {
+        const double res = bn2[r] > 0 ? std::sqrt(rn2[r] / bn2[r]) : 0.0;
+        OVL_REQUIRE(std::isfinite(res), OVL_E_NAN, "true residual is NaN or Inf");
+        st->true_residual[r] = res;
+        active[r] = res > tol;
+        if (active[r]) done = false;
+      }
+      if (done) break;
+      if (its >= maxiter || st->restarts >= max_restarts) {
+        rc = OVL_W_NOT_CONVERGED;
+        break;
+      }
+      ++st->restarts;
+      // scaled inner system D e = r / scale
+      std::vector<double> scale(R), isc(2 * OVL_MAX_RHS, 0.0), target(R);
+      for (int r = 0; r < R; ++r) {
+        const double rn = std::sqrt(rn2[r]);
+        scale[r] = active[r] ? rn / rms_target : 0.0;
+        isc[2 * r] = active[r] ? 1.0 / scale[r] : 0.0;
+        double rel = active[r] ? 0.5 * tol * std::sqrt(bn2[r]) / rn : 1.0;
+        if (P != OVL_F64) rel = std::max(rel, inner_tol);
+        target[r] = std::min(rel, 1.0) * rms_target;
+      }
+      dev_scalars(isc);
+      blas_axpby(OVL_F64, r64.p, dsc, OVL_F64, rin.p, nullptr, N, R, s);
+      blas_zero(e64.p, v64 * R, s);
+      std::vector<double> rnorm(R);
+      for (int r = 0; r < R; ++r) rnorm[r] = active[r] ? rms_target : 0.0;
+      bool inner_done = false;
+      while (!inner_done && its < maxiter) {
+        std::vector<double> cycle_start = rnorm;
+        int j = 0;
+        for (; j < restart && its < maxiter; ++j) {
+          // z = M r (FP32 network) or z = r, then w = D(m) z at the inner precision
+          if (net) {
+            blas_convert(OVL_F64, rin.p, OVL_F32, r32.p, N, R, s);
+            for (int r = 0; r < R; ++r)
+              if (active[r]) net_apply(net, u, vec(r32.p, v32, r), vec(z32.p, v32, r), s);
+            blas_convert(OVL_F32, z32.p, P, zP.p, N, R, s);
+          } else {
+            blas_convert(OVL_F64, rin.p, P, zP.p, N, R, s);
+          }
+          dm(wP.p, zP.p, P);
+          blas_convert(P, wP.p, OVL_F64, w64.p, N, R, s);
+          blas_convert(P, zP.p, OVL_F64, z64.p, N, R, s);
+          ++its;
+          bool any = false;
+          for (int r = 0; r < R; ++r) {
+            if (!active[r]) continue;
+            char* wr = vec(w64.p, v64, r);
+            char* zr = vec(z64.p, v64, r);
+            char* Wr = vec(Wb.p, v64, r * restart);
+            char* Zr = vec(Zb.p, v64, r * restart);
+            for (int pass = 0; pass < (j > 0 ? 2 : 0); ++pass) {
+              block_dot(g, Wr, j, wr, OVL_F64, 1, static_cast<double2*>(cb.p), s);
+              std::vector<double2> hc(j);
+              OVL_HIP(hipMemcpyAsync(hc.data(), cb.p, sizeof(double2) * j, hipMemcpyDeviceToHost, s));
+              OVL_HIP(hipStreamSynchronize(s));
+              for (auto& v : hc) v = make_double2(-v.x, -v.y);
+              OVL_HIP(hipMemcpyAsync(cb.p, hc.data(), sizeof(double2) * j, hipMemcpyHostToDevice, s));
+              block_axpy(g, Wr, j, static_cast<const double2*>(cb.p), wr, OVL_F64, 1, true, s);
+              block_axpy(g, Zr, j, static_cast<const double2*>(cb.p), zr, OVL_F64, 1, true, s);
+              OVL_HIP(hipStreamSynchronize(s));
+            }
+            std::vector<double> nw;
+            norms(wr, 1, v64, OVL_F64, nw);
+            const double nrm = std::sqrt(nw[0]);
+            if (!(nrm > 0.0) || !std::isfinite(nrm)) {
+              fallback = true;
+              break;
+            }
+            std::vector<double> sv = {1.0 / nrm, 0.0};
+            dev_scalars(sv);
+            blas_axpby(OVL_F64, wr, dsc, OVL_F64, vec(Wr, v64, j), nullptr, N, 1, s);
+            blas_axpby(OVL_F64, zr, dsc, OVL_F64, vec(Zr, v64, j), nullptr, N, 1, s);
+            const std::complex<double> alpha = dot1(vec(Wr, v64, j), vec(rin.p, v64, r));
+            axpy1(vec(Zr, v64, j), vec(e64.p, v64, r), alpha);
+            axpy1(vec(Wr, v64, j), vec(rin.p, v64, r), -alpha);
+            std::vector<double> rr;
+            norms(vec(rin.p, v64, r), 1, v64, OVL_F64, rr);
+            rnorm[r] = std::sqrt(rr[0]);
+            if (!std::isfinite(rnorm[r])) {
+              fallback = true;
+              break;
+            }
+            if (rnorm[r] <= target[r]) active[r] = 0;
+            any = any || active[r];
+          }
+          if (fallback || !any) break;
+        }
+        if (fallback) break;
+        bool any = false, stagnant = false;
+        for (int r = 0; r < R; ++r)
+          if (active[r]) {
+            any = true;
+            if (j >= restart && rnorm[r] > 0.9 * cycle_start[r]) stagnant = true;
+          }
+        if (stagnant) fallback = true;
+        inner_done = !any || fallback;
+      }
+      // x += scale * e
+      std::vector<double> scv(2 * OVL_MAX_RHS, 0.0);
+      for (int r = 0; r < R; ++r) scv[2 * r] = scale[r];
+      dev_scalars(scv);
+      std::vector<double> onev(2 * OVL_MAX_RHS, 0.0);
+      WsBuf oneb(sizeof(double) * 2 * OVL_MAX_RHS, s);
+      for (int r = 0; r < R; ++r) onev[2 * r] = 1.0;
+      OVL_HIP(hipMemcpyAsync(oneb.p, onev.data(), sizeof(double) * onev.size(), hipMemcpyHostToDevice, s));
+      OVL_HIP(hipStreamSynchronize(s));
+      blas_axpby(OVL_F64, e64.p, dsc, OVL_F64, x, static_cast<double*>(oneb.p), N, R, s);
+      OVL_HIP(hipStreamSynchronize(s));
+      if (fallback) break;
+    }
+    st->iterations = its;
+  } catch (...) {
+    (void)hipStreamSynchronize(s);
+    (void)hipEventDestroy(ev);
+    (void)hipStreamDestroy(s);
+    throw;
+  }
+  OVL_HIP(hipEventRecord(ev, s));
+  OVL_HIP(hipStreamWaitEvent(us, ev, 0));
+  OVL_HIP(hipStreamSynchronize(s));
+  OVL_HIP(hipEventDestroy(ev));
+  OVL_HIP(hipStreamDestroy(s));
+  if (fallback) {
+    // plain CG finishes the solve from the current x
+    ovl_solve_stats cs{};
+    ovl_solve_opts co{};
+    co.inner_prec = static_cast<ovl_prec>(P);
+    co.inner_tol = inner_tol;
+    co.graph_chunk = o ? o->graph_chunk : 0;
+    co.check_every = 1;
+    co.max_restarts = max_restarts;
+    const int its0 = st->iterations;
+    const int64_t sa = st->sign_applies, da = st->dslash_applies;
+    rc = cg_solve(x, b, R, u, rho, m, sg, lm, tol, std::max(0, maxiter - its0), &co, &cs, us);
+    *st = cs;
+    st->iterations += its0;
+    st->sign_applies += sa;
+    st->dslash_applies += da;
+    st->fallback_used = 1;
+  }
+  st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  return rc;
+}
+
 }  // namespace ovl
 
 using namespace ovl;
@@ -320,6 +576,22 @@ int ovl_cg_solve(void* x, const void* b, int nrhs, const ovl_gauge* u, double rh
     if (opts) OVL_REQUIRE(opts->graph_chunk >= 0 && opts->graph_chunk <= 1000, OVL_E_ARG, "graph_chunk out of range");
     *stats = ovl_solve_stats{};
     return cg_solve(x, b, nrhs, u, rho, m, sign, lowmodes, tol, maxiter, opts, stats, static_cast<hipStream_t>(s));
+  });
+}
+
+int ovl_fgcr_solve(void* x, const void* b, int nrhs, const ovl_gauge* u, double rho, double m, const ovl_sign* sign,
+                   const ovl_lowmodes* lowmodes, const ovl_net* M, int restart, double tol, int maxiter,
+                   const ovl_solve_opts* opts, ovl_solve_stats* stats, ovl_stream_t s) {
+  return guard([&] {
+    OVL_REQUIRE(x && b && u && sign && stats, OVL_E_ARG, "null argument");
+    OVL_REQUIRE(nrhs >= 1 && nrhs <= OVL_MAX_RHS, OVL_E_ARG, "fgcr_solve: 1 <= nrhs <= 12");
+    OVL_REQUIRE(restart >= 1 && restart <= 32, OVL_E_ARG, "fgcr_solve: 1 <= restart <= 32");
+    OVL_REQUIRE(x != b, OVL_E_ALIAS, "x must not alias b");
+    OVL_REQUIRE(tol > 0.0 && maxiter >= 0, OVL_E_ARG, "need tol > 0 and maxiter >= 0");
+    if (lowmodes && lowmodes->ell == 0) lowmodes = nullptr;
+    *stats = ovl_solve_stats{};
+    return fgcr_solve(x, b, nrhs, u, rho, m, sign, lowmodes, M, restart, tol, maxiter, opts, stats,
+                      static_cast<hipStream_t>(s));
   });
 }
 

@@ -76,6 +76,9 @@ class SolveOpts(ctypes.Structure):
         ("graph_chunk", ctypes.c_int),
         ("check_every", ctypes.c_int),
         ("max_restarts", ctypes.c_int),
+        ("harvest_x", ctypes.c_void_p),
+        ("harvest_b", ctypes.c_void_p),
+        ("harvest_cap", ctypes.c_int),
     ]
 
 
@@ -97,6 +100,7 @@ class SolveStats(ctypes.Structure):
         ("sign_applies", ctypes.c_int64),
         ("dslash_applies", ctypes.c_int64),
         ("fallback_used", ctypes.c_int),
+        ("harvested", ctypes.c_int),
     ]
 
 
@@ -145,6 +149,15 @@ _SIGS = {
     "ovl_hw_bound": (P, D, P, I, P, P, P, ST),
     "ovl_hw_eigs": (P, D, I, I, P, P, D, D, I, I, P, ST),
     "ovl_host_heev": (I, P, P, P),
+    "ovl_fgcr_solve": (P, P, I, P, D, D, P, P, P, I, D, I, P, P, ST),
+    "ovl_net_create": (P, I, P),
+    "ovl_net_destroy": (P,),
+    "ovl_net_set_weights": (P, P, P),
+    "ovl_net_get_weights": (P, P, P),
+    "ovl_ptc_layer_forward": (P, P, I, P, I, P, ST),
+    "ovl_ptc_layer_backward": (P, P, I, P, I, P, P, P, ST),
+    "ovl_net_train": (P, P, P, P, I, I, I, D, P, P, ST),
+    "ovl_net_apply": (P, P, P, P, ST),
 }
 
 EXPORTED = ["ovl_last_error", "ovl_version", "ovl_gauge_geom"] + list(_SIGS)
@@ -314,4 +327,31 @@ class LowModes:
     def __del__(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
             lib.ovl_lowmodes_destroy(self.handle)
+            self.handle = None
+
+
+class Net:
+    """Two-layer PTC network 1 -> hidden -> 1 (weights held by the library)."""
+
+    def __init__(self, geom, hidden=4):
+        h = ctypes.c_void_p()
+        ovl_net_create(geom.handle, hidden, ctypes.byref(h))
+        self.handle = h
+        self.hidden = hidden
+
+    def set_weights(self, w1, w2):
+        w1 = np.ascontiguousarray(w1, dtype=np.complex128)
+        w2 = np.ascontiguousarray(w2, dtype=np.complex128)
+        assert w1.size == 9 * self.hidden * 16 and w2.size == 9 * self.hidden * 16
+        ovl_net_set_weights(self.handle, w1, w2)
+
+    def get_weights(self):
+        w1 = np.zeros((9, self.hidden, 1, 4, 4), dtype=np.complex128)
+        w2 = np.zeros((9, 1, self.hidden, 4, 4), dtype=np.complex128)
+        ovl_net_get_weights(self.handle, w1, w2)
+        return w1, w2
+
+    def __del__(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib.ovl_net_destroy(self.handle)
             self.handle = None
