@@ -52,7 +52,7 @@ def parse():
     ap.add_argument("--delta", type=float, default=1e-10)
     ap.add_argument("--prec", type=str, default="f16")
     ap.add_argument("--no-cg", action="store_true")
-    ap.add_argument("--fp64-cg-rhs", type=int, default=12, help="rhs of the plain FP64 CG comparison")
+    ap.add_argument("--fp64-cg-rhs", type=int, default=1, help="rhs of the plain FP64 CG comparison (time scaled to 12)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-only", action="store_true", help=argparse.SUPPRESS)
     return ap.parse_args()
@@ -118,6 +118,7 @@ def main():
               "has no multi-GPU path (--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
+    os.environ.setdefault("OVL_LOG", "1")  # solver progress lines on stderr
     import numpy as np
     import torch
 

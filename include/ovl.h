@@ -340,6 +340,20 @@ int ovl_net_train(ovl_net* n, const ovl_gauge* u, const void* B, const void* X, 
                   double lr, const int32_t* order, double* loss_history, ovl_stream_t s);
 int ovl_net_apply(const ovl_net* n, const ovl_gauge* u, const void* in, void* out, ovl_stream_t s);
 
+/* ovl_stencil_tune: mode 1 (default; OVL_TUNE=0 in the environment starts
+ *   with 0) times every candidate shape of a stencil configuration once,
+ *   with HIP events on a scratch output, and keeps the fastest: KR
+ *   right-hand sides per thread (each link loaded once per KR vectors; KR
+ *   divides nrhs, KR <= 4, <= 2 for FP64) and 128 or 256 threads per block.
+ *   Mode 0 uses the largest allowed KR and 256 threads.  Changing the mode
+ *   clears the tuned table.  Launches inside a HIP graph capture never tune.
+ * ovl_stencil_shape: the tuned (kr, bs) of a full-lattice configuration
+ *   (precision, link compression, number of extra epilogue vectors 0..3,
+ *   batch size); kr = bs = 0 when it has not been tuned yet.
+ */
+int ovl_stencil_tune(int mode);
+int ovl_stencil_shape(const ovl_geom* g, ovl_prec prec, int compress12, int nextra, int nrhs, int* kr, int* bs);
+
 /* ovl_counters: stencil launches and vector applications of D_w issued from
  * the host since the last reset (graph replays are not seen here).
  */

@@ -82,6 +82,24 @@ const char* ovl_last_error(void) { return g_last_error.c_str(); }
 
 int ovl_version(void) { return 100; }
 
+int ovl_stencil_tune(int mode) {
+  return guard([&] {
+    OVL_REQUIRE(mode == 0 || mode == 1, OVL_E_ARG, "tune mode must be 0 or 1");
+    set_tune_mode(mode);
+    return OVL_OK;
+  });
+}
+
+int ovl_stencil_shape(const ovl_geom* g, ovl_prec prec, int compress12, int nextra, int nrhs, int* kr, int* bs) {
+  return guard([&] {
+    OVL_REQUIRE(g && kr && bs, OVL_E_ARG, "null argument");
+    *kr = 0;
+    *bs = 0;
+    stencil_shape(prec, compress12 ? 12 : 18, nextra, nrhs, 2, g->geo.Nh, kr, bs);
+    return OVL_OK;
+  });
+}
+
 int ovl_counters(int64_t* stencil_launches, int64_t* stencil_vectors, int reset) {
   if (stencil_launches) *stencil_launches = g_stencil_launches.load();
   if (stencil_vectors) *stencil_vectors = g_stencil_vectors.load();

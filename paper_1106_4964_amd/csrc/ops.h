@@ -28,6 +28,12 @@ struct StencilArgs {
 };
 
 void launch_stencil(const StencilArgs& A, int prec, int recon, int nrhs, hipStream_t s);
+// Stencil shape selection: mode 1 autotunes (default), 0 uses the static
+// default (largest KR <= 4, <= 2 for FP64, dividing nrhs; 256 threads).
+// Changing the mode clears the tuned table.
+void set_tune_mode(int mode);
+// Tuned shape of a configuration, if any: returns 1 and fills kr, bs.
+int stencil_shape(int prec, int recon, int nv, int nrhs, int npar, int nh, int* kr, int* bs);
 
 // Representation of the links that operators at spinor precision prec use.
 const void* gauge_links(const ovl_gauge* u, int prec, int* recon);

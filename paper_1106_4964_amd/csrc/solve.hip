@@ -16,11 +16,23 @@
 // between replays.
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 
 #include "ops.h"
 
 namespace ovl {
 namespace {
+
+// OVL_LOG=1 in the environment: one line per outer cycle and every 100
+// inner iterations on stderr (residual history of a running solve).
+bool log_on() {
+  static const bool on = [] {
+    const char* e = std::getenv("OVL_LOG");
+    return e && *e && *e != '0';
+  }();
+  return on;
+}
 
 // Scalars of one inner solve, all device-resident, one slot per rhs.
 struct Scalars {
@@ -219,12 +231,16 @@ int cg_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, doub
       OVL_HIP(hipMemcpyAsync(rn2.data(), dS->rrn, sizeof(double) * R, hipMemcpyDeviceToHost, s));
       OVL_HIP(hipStreamSynchronize(s));
       bool done = true;
+      double worst = 0.0;
       for (int r = 0; r < R; ++r) {
         const double res = bn2[r] > 0 ? std::sqrt(rn2[r] / bn2[r]) : 0.0;
         OVL_REQUIRE(std::isfinite(res), OVL_E_NAN, "true residual is NaN or Inf");
         st->true_residual[r] = res;
+        worst = std::max(worst, res);
         if (res > tol) done = false;
       }
+      if (log_on())
+        fprintf(stderr, "[ovl cg] cycle %d: %d iterations, max FP64 true residual %.3e\n", st->restarts, its, worst);
       if (done) break;
       if (its >= maxiter || st->restarts >= opt.max_restarts) {
         rc = OVL_W_NOT_CONVERGED;
@@ -282,6 +298,8 @@ int cg_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, doub
           for (int k = 0; k < nrun; ++k) body();
           step = nrun;
         }
+        if (log_on() && (its + step) / 100 != its / 100)
+          fprintf(stderr, "[ovl cg]   inner iteration %d\n", its + step);
         inner += step;
         its += step;
         OVL_HIP(hipMemcpyAsync(hS.active, dS->active, sizeof(hS.active) + sizeof(hS.bad), hipMemcpyDeviceToHost, s));
@@ -416,6 +434,11 @@ int fgcr_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, do
         st->true_residual[r] = res;
         active[r] = res > tol;
         if (active[r]) done = false;
+      }
+      if (log_on()) {
+        double worst = 0.0;
+        for (int r = 0; r < R; ++r) worst = std::max(worst, st->true_residual[r]);
+        fprintf(stderr, "[ovl fgcr] cycle %d: %d iterations, max FP64 true residual %.3e\n", st->restarts, its, worst);
       }
       if (done) break;
       if (its >= maxiter || st->restarts >= max_restarts) {

@@ -146,6 +146,8 @@ _SIGS = {
     "ovl_cg_solve": (P, P, I, P, D, D, P, P, D, I, P, P, ST),
     "ovl_propagator": (P, P, P, D, P, P, I, I, ST),
     "ovl_counters": (P, P, I),
+    "ovl_stencil_tune": (I,),
+    "ovl_stencil_shape": (P, I, I, I, I, P, P),
     "ovl_hw_bound": (P, D, P, I, P, P, P, ST),
     "ovl_hw_eigs": (P, D, I, I, P, P, D, D, I, I, P, ST),
     "ovl_host_heev": (I, P, P, P),

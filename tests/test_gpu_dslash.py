@@ -1,4 +1,6 @@
 """GPU parity of geometry, packing and the Wilson stencil against the oracle."""
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -130,3 +132,41 @@ def test_dslash_full_size_24x64():
     dims = (24, 24, 24, 64)
     got, want = _dslash_case(dims, ovl.OVL_F64, 0, -1.5, 2, seed=5)
     assert gu.max_rel_err(got, want) < 1e-13
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_every_vectors_per_thread_shape(prec):
+    """Static shapes KR = 1..4 (batch sizes 1..4) and a tuned 12-rhs batch all
+    give the same values as one-vector calls."""
+    dims = (6, 6, 6, 8)
+    lat = Lattice(dims)
+    U = si.gauge_field(dims, 0.25, 4)
+    g = ovl.Geometry(dims)
+    gauge = gu.make_gauge(g, U, [] if prec == ovl.OVL_F64 else [(prec, 1)])
+    psi = np.stack([si.gaussian_spinor(dims, 300 + r) for r in range(12)])
+    inp = gu.pack(g, psi, prec, 12)
+    vb = g.spinor_bytes(prec)
+    single = gu.empty_field(g, prec, 12)
+    ovl.ovl_stencil_tune(0)
+    try:
+        for r in range(12):
+            ovl.ovl_dslash(single[r * vb:], inp[r * vb:], gauge, -0.3, 2, prec, 1, None)
+        want = gu.unpack(g, single, prec, 12)
+        for nrhs in (2, 3, 4):
+            if prec == ovl.OVL_F64 and nrhs > 2:
+                continue
+            out = gu.empty_field(g, prec, nrhs)
+            ovl.ovl_dslash(out, inp, gauge, -0.3, 2, prec, nrhs, None)
+            got = gu.unpack(g, out, prec, nrhs)
+            assert gu.max_rel_err(got, want[:nrhs]) <= 2 * gu.UNIT_ROUNDOFF[prec]
+    finally:
+        ovl.ovl_stencil_tune(1)
+    out = gu.empty_field(g, prec, 12)
+    ovl.ovl_dslash(out, inp, gauge, -0.3, 2, prec, 12, None)
+    kr, bs = ctypes.c_int(), ctypes.c_int()
+    ovl.ovl_stencil_shape(g, prec, 0 if prec == ovl.OVL_F64 else 1, 0, 12, ctypes.byref(kr), ctypes.byref(bs))
+    assert kr.value in (1, 2, 3, 4) and bs.value in (128, 256)
+    got = gu.unpack(g, out, prec, 12)
+    assert gu.max_rel_err(got, want) <= 2 * gu.UNIT_ROUNDOFF[prec]
+    ref = dirac.wilson_dslash(lat, U, psi[5], -0.3)
+    assert gu.rel_err(got[5], ref) < 16 * gu.UNIT_ROUNDOFF[prec] + 4e-7
