@@ -52,8 +52,17 @@ def parse():
     ap.add_argument("--delta", type=float, default=1e-10)
     ap.add_argument("--prec", type=str, default="f16")
     ap.add_argument("--no-cg", action="store_true")
-    ap.add_argument("--fp64-cg-rhs", type=int, default=1, help="rhs of the plain FP64 CG comparison (time scaled to 12)")
+    ap.add_argument("--cg-masses", type=str, default="0.01")
+    ap.add_argument("--inner-delta", type=float, default=1e-4,
+                    help="sign accuracy of the inner (low-precision) operator; 0 = same as outer")
+    ap.add_argument("--inner-tol", type=float, default=1e-3)
+    ap.add_argument("--graph-chunk", type=int, default=8)
+    ap.add_argument("--fp64-cg-rhs", type=int, default=1,
+                    help="rhs of the plain FP64 CG comparison (time scaled to 12); 0 = skip")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--mode", choices=["full", "kernels"], default="full",
+                    help="kernels: only a 1 GiB calibration copy and the stencil configurations "
+                         "(for rocprofv3 counter passes)")
     ap.add_argument("--cpu-only", action="store_true", help=argparse.SUPPRESS)
     return ap.parse_args()
 
@@ -107,6 +116,49 @@ def cpu_baseline(dims, n, ell):
 
 
 # ---------------------------------------------------------------------------
+# Counter runs: a plain copy of known size, then each stencil configuration
+# ---------------------------------------------------------------------------
+def kernels_mode(dims, prec_name):
+    import numpy as np
+    import torch
+
+    import synth_inputs as si
+    from paper_1106_4964_amd import ovl
+
+    dev = torch.device("cuda:0")
+    prec = ovl.PREC[prec_name]
+    g = ovl.Geometry(dims)
+    U = si.gauge_field(dims, 0.25, 3)
+    gauge = ovl.Gauge(g, torch.from_numpy(U).to(dev))
+    del U
+    gauge.set_repr(prec, 1)
+    gauge.set_repr(ovl.OVL_F32, 1)
+    src = torch.from_numpy(np.stack([si.gaussian_spinor(dims, 500 + r) for r in range(12)])).to(dev)
+    b64 = torch.empty(g.spinor_bytes(ovl.OVL_F64, 12), dtype=torch.uint8, device=dev)
+    ovl.ovl_pack_spinor(g, src, b64, ovl.OVL_F64, 12, None)
+    del src
+    # calibration: copy 1 GiB (reads 1 GiB, writes 1 GiB)
+    a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+    c = torch.empty_like(a)
+    for _ in range(3):
+        c.copy_(a)
+    torch.cuda.synchronize()
+    log("calibration copy: %d bytes read and written per launch" % (a.numel() * 4))
+    del a, c
+    for name, p, nrhs in [("f16_12_12rhs", prec, 12), ("f16_12_1rhs", prec, 1),
+                          ("f32_12_1rhs", ovl.OVL_F32, 1), ("f64_18_1rhs", ovl.OVL_F64, 1)]:
+        x = torch.empty(g.spinor_bytes(p, nrhs), dtype=torch.uint8, device=dev)
+        ovl.ovl_convert(g, b64[: g.spinor_bytes(ovl.OVL_F64, nrhs)], ovl.OVL_F64, x, p, nrhs, None)
+        y = torch.empty_like(x)
+        ovl.ovl_hw_apply(y, x, gauge, 1.5, p, nrhs, None)  # tunes the shape
+        torch.cuda.synchronize()
+        for _ in range(3):
+            ovl.ovl_hw_apply(y, x, gauge, 1.5, p, nrhs, None)
+        torch.cuda.synchronize()
+        log("stencil %s: shape (kr, bs, pipe, rin, tm) = %s" % (name, ovl.stencil_shape(g, p, p != ovl.OVL_F64, 0, nrhs)))
+
+
+# ---------------------------------------------------------------------------
 def main():
     args = parse()
     dims = tuple(int(v) for v in args.dims.split(","))
@@ -118,6 +170,9 @@ def main():
               "has no multi-GPU path (--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
+    if args.mode == "kernels":
+        kernels_mode(dims, args.prec)
+        return
     os.environ.setdefault("OVL_LOG", "1")  # solver progress lines on stderr
     import numpy as np
     import torch
@@ -187,11 +242,20 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    ovl.ovl_stencil_timer(1)  # HIP events around every stencil launch of the timed steps
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step()
     torch.cuda.synchronize()
     t_steps = time.perf_counter() - t0
+    ovl.ovl_stencil_timer(0)
+    step_kernels = {}
+    for nv in range(4):
+        n_l, ms_l = ovl.stencil_timer_read(prec, 1, nv, R)
+        if n_l:
+            step_kernels[nv] = (n_l, ms_l)
+            log("timed steps: stencil f16-12 %d rhs, %d extra vectors: %d launches, avg %.1f us, %.1f%% of step time"
+                % (R, nv, n_l, 1e3 * ms_l / n_l, 100.0 * ms_l / (1e3 * t_steps)))
     ms_per_step = 1e3 * t_steps / args.steps
     applies_per_s = 2 * R * args.steps / t_steps
     log("step %.2f ms -> %.1f D_ov applies/s" % (ms_per_step, applies_per_s))
@@ -216,10 +280,10 @@ def main():
 
     bytes_per_real = {ovl.OVL_F64: 8, ovl.OVL_F32: 4, ovl.OVL_F16: 2, ovl.OVL_BF16: 2}
 
-    def model_bytes(p, L, nrhs):
+    def model_bytes(p, L, nrhs, nv=0):
         # compulsory traffic, full lattice, one pass: links once per launch,
-        # each input and output spinor once
-        return N * bytes_per_real[p] * (4 * L + 48 * nrhs)
+        # each input and output spinor once, each extra epilogue vector once
+        return N * bytes_per_real[p] * (4 * L + 48 * nrhs + 24 * nv * nrhs)
 
     dslash = {}
     gauge.set_repr(ovl.OVL_F64, 0)
@@ -228,20 +292,28 @@ def main():
         t = stencil_time(p, nrhs)
         gbs = model_bytes(p, L, nrhs) / t / 1e9
         dslash[name] = {"us": round(t * 1e6, 2), "model_GBps": round(gbs, 1),
-                        "gflops": round(1368.0 * N * nrhs / t / 1e9, 1)}
+                        "gflops": round(1368.0 * N * nrhs / t / 1e9, 1),
+                        "shape": list(ovl.stencil_shape(g, p, p != ovl.OVL_F64, 0, nrhs))}
         log("dslash %s: %.1f us, %.0f GB/s (model bytes)" % (name, t * 1e6, gbs))
-    dom = dslash["f16_12_12rhs"]
-    dom_bytes = model_bytes(prec, 12, 12)
+    # dominant kernel of the timed steps: the stencil configuration with the
+    # largest summed launch time, its average launch measured with HIP events
+    dom_nv = max(step_kernels, key=lambda k: step_kernels[k][1])
+    n_dom, ms_dom = step_kernels[dom_nv]
+    dom_us = 1e3 * ms_dom / n_dom
+    dom_bytes = model_bytes(prec, 12, R, dom_nv)
+    dom_gbs = dom_bytes / (dom_us * 1e-6) / 1e9
     roofline = {
         "bound": "hbm",
-        "achieved": dom["model_GBps"],
+        "achieved": round(dom_gbs, 1),
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
-        "frac": round(dom["model_GBps"] / HBM_PEAK_GBS, 4),
+        "frac": round(dom_gbs / HBM_PEAK_GBS, 4),
         "traffic": None,
-        "kernel": "stencil_kernel<F16, 12-real links, 0 extra vectors>, 12 rhs, 24^3x64",
+        "kernel": "stencil_kernel<F16, 12-real links, %d extra vectors>, %d rhs, %s" % (dom_nv, R, "x".join(map(str, dims))),
         "bytes_per_launch": dom_bytes,
-        "avg_launch_us": dom["us"],
+        "avg_launch_us": round(dom_us, 2),
+        "launches": n_dom,
+        "share_of_step": round(ms_dom / (1e3 * t_steps), 4),
     }
 
     # ----------------------------------------------------------------- CG
@@ -249,9 +321,16 @@ def main():
     if not args.no_cg:
         cg = {}
 
-        def solve(p, nrhs, m, graph, inner_tol):
+        sgn_in = None
+        if args.inner_delta > 0:
+            sgn_in = ovl.Sign(abs(lams[-1]), lam_max, delta=args.inner_delta)
+            log("inner sign: n = %d (delta %.1e)" % (sgn_in.n, sgn_in.delta))
+            cg["inner_sign_order"] = sgn_in.n
+
+        def solve(p, nrhs, m, graph, inner_tol, inner_sign=None):
             x = torch.zeros(g.spinor_bytes(ovl.OVL_F64, nrhs), dtype=torch.uint8, device=dev)
-            opts = ovl.SolveOpts(p, inner_tol, graph, 1, 60)
+            opts = ovl.SolveOpts(p, inner_tol, graph, 1, 60, None, None, 0,
+                                 inner_sign.handle.value if inner_sign is not None else None)
             st = ovl.SolveStats()
             rc = ovl.ovl_cg_solve(x, b64[: g.spinor_bytes(ovl.OVL_F64, nrhs)], nrhs, gauge, rho, m, sgn, lm,
                                   1e-10, 20000, opts, st, None)
@@ -259,18 +338,22 @@ def main():
             return {"rc": rc, "seconds": round(st.seconds, 3), "iterations": st.iterations,
                     "restarts": st.restarts, "max_true_residual": res, "sign_applies": st.sign_applies}
 
-        for m in masses:
-            r_mixed = solve(prec, R, m, 8, 1e-3)
+        for m in [float(v) for v in args.cg_masses.split(",")]:
+            r_mixed = solve(prec, R, m, args.graph_chunk, args.inner_tol, sgn_in)
             log("CG mixed m=%.2f: %s" % (m, r_mixed))
             cg["mixed_f16_12rhs_m%.2f" % m] = r_mixed
-        nfp = max(1, min(R, args.fp64_cg_rhs))
-        r64 = solve(ovl.OVL_F64, nfp, masses[0], 0, 0.0)
-        log("CG plain FP64 m=%.2f (%d rhs): %s" % (masses[0], nfp, r64))
-        cg["plain_f64_m%.2f_%drhs" % (masses[0], nfp)] = r64
-        t64 = r64["seconds"] * (R / nfp)
-        cg["speedup_vs_plain_f64_m%.2f" % masses[0]] = round(t64 / cg["mixed_f16_12rhs_m%.2f" % masses[0]]["seconds"], 2)
-        if nfp < R:
-            cg["note"] = "plain FP64 time scaled from %d to 12 rhs" % nfp
+        if args.fp64_cg_rhs > 0:
+            nfp = min(R, args.fp64_cg_rhs)
+            m0 = float(args.cg_masses.split(",")[0])
+            r64 = solve(ovl.OVL_F64, nfp, m0, 0, 0.0)
+            log("CG plain FP64 m=%.2f (%d rhs): %s" % (m0, nfp, r64))
+            cg["plain_f64_m%.2f_%drhs" % (m0, nfp)] = r64
+            t64 = r64["seconds"] * (R / nfp)
+            cg["plain_f64_12rhs_seconds"] = round(t64, 2)
+            cg["speedup_vs_plain_f64_m%.2f" % m0] = round(t64 / cg["mixed_f16_12rhs_m%.2f" % m0]["seconds"], 2)
+            if nfp < R:
+                cg["note"] = ("plain FP64 time measured on %d of the 12 point sources and scaled by 12/%d "
+                              "(FP64 solves gain nothing from batching)" % (nfp, nfp))
 
     cpu = None
     if not args.no_cpu:

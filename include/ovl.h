@@ -224,6 +224,11 @@ int ovl_overlap_apply(void* out, const void* in, const ovl_gauge* u, double rho,
  *   converges is frozen (its scalars become zero) while the others go on.
  *   Returns OVL_OK, OVL_W_NOT_CONVERGED (maxiter inner iterations or
  *   max_restarts cycles reached; stats valid), OVL_E_BREAKDOWN or OVL_E_NAN.
+ *   The inner operator may use a relaxed sign approximation
+ *   (opts->inner_sign): the inner solve only has to reduce the residual by
+ *   inner_tol, so its sign function need not be more accurate than that
+ *   (adaptive precision, Sec. V); the defect correction still converges to
+ *   the FP64 operator built from `sign`.
  *   opts may be NULL (plain FP64, no graph).  Work is done on a private
  *   stream ordered after, and before, the caller's stream s.
  * ovl_propagator: out = (1 - D/2) x (Sec. II), the propagator from a
@@ -238,6 +243,10 @@ typedef struct {
   void* harvest_x;     /* CG only: FP32 buffers that receive exact pairs  */
   void* harvest_b;     /*   (x, b = D(m) x) from the CG matvecs; NULL=off */
   int harvest_cap;     /*   capacity of each buffer, in spinors           */
+  const ovl_sign* inner_sign; /* sign approximation of the inner operator
+                                 (same lam_max; typically a larger delta, so
+                                 a lower order); NULL = the outer one.  The
+                                 FP64 true residual always uses `sign`.   */
 } ovl_solve_opts;
 
 typedef struct {
@@ -347,12 +356,36 @@ int ovl_net_apply(const ovl_net* n, const ovl_gauge* u, const void* in, void* ou
  *   divides nrhs, KR <= 4, <= 2 for FP64) and 128 or 256 threads per block.
  *   Mode 0 uses the largest allowed KR and 256 threads.  Changing the mode
  *   clears the tuned table.  Launches inside a HIP graph capture never tune.
- * ovl_stencil_shape: the tuned (kr, bs) of a full-lattice configuration
- *   (precision, link compression, number of extra epilogue vectors 0..3,
- *   batch size); kr = bs = 0 when it has not been tuned yet.
+ *   Candidate shapes: (a) KR vectors per thread, one lattice pass per
+ *   group of KR vectors, 128 or 256 threads; (b) the same with all
+ *   nrhs/KR groups side by side in one workgroup (32 or 64 sites x groups
+ *   threads, at most 512); (c) one-vector kernels that issue the loads of
+ *   the next 1..3 directions before the arithmetic of the current one
+ *   (pipeline depth 2..4); each in h order or in t-major order (blocks of a
+ *   parity walk t for a fixed tile of the x-y-z half slice, so that
+ *   t-neighbours come from cache).
+ * ovl_stencil_shape: shape[5] = {kr, bs, pipe, rin, tm} tuned for a
+ *   full-lattice configuration (precision, link compression, number of
+ *   extra epilogue vectors 0..3, batch size); all 0 when it has not been
+ *   tuned yet.
+ * ovl_stencil_set_shape: pins shape[5] for a configuration (all parity
+ *   choices); OVL_E_ARG for shapes the kernels do not support.
  */
 int ovl_stencil_tune(int mode);
-int ovl_stencil_shape(const ovl_geom* g, ovl_prec prec, int compress12, int nextra, int nrhs, int* kr, int* bs);
+int ovl_stencil_shape(const ovl_geom* g, ovl_prec prec, int compress12, int nextra, int nrhs, int* shape);
+int ovl_stencil_set_shape(const ovl_geom* g, ovl_prec prec, int compress12, int nextra, int nrhs, const int* shape);
+
+/* ovl_stencil_timer: per-configuration launch timing of the stencil kernels
+ *   with HIP events recorded on the launch stream around every launch that
+ *   is not being captured into a graph.  mode 1 clears and enables, 0
+ *   disables (keeps what was measured), 2 clears.
+ * ovl_stencil_timer_read: launches and summed kernel milliseconds of one
+ *   configuration (precision, link compression, extra epilogue vectors 0..3,
+ *   batch size) since the last clear; waits for the recorded events.
+ */
+int ovl_stencil_timer(int mode);
+int ovl_stencil_timer_read(ovl_prec prec, int compress12, int nextra, int nrhs, int64_t* launches,
+                           double* total_ms);
 
 /* ovl_counters: stencil launches and vector applications of D_w issued from
  * the host since the last reset (graph replays are not seen here).

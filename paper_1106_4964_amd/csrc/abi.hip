@@ -90,12 +90,52 @@ int ovl_stencil_tune(int mode) {
   });
 }
 
-int ovl_stencil_shape(const ovl_geom* g, ovl_prec prec, int compress12, int nextra, int nrhs, int* kr, int* bs) {
+int ovl_stencil_shape(const ovl_geom* g, ovl_prec prec, int compress12, int nextra, int nrhs, int* shape) {
   return guard([&] {
-    OVL_REQUIRE(g && kr && bs, OVL_E_ARG, "null argument");
-    *kr = 0;
-    *bs = 0;
-    stencil_shape(prec, compress12 ? 12 : 18, nextra, nrhs, 2, g->geo.Nh, kr, bs);
+    OVL_REQUIRE(g && shape, OVL_E_ARG, "null argument");
+    for (int i = 0; i < 5; ++i) shape[i] = 0;
+    stencil_shape(prec, compress12 ? 12 : 18, nextra, nrhs, 2, g->geo.Nh, shape);
+    return OVL_OK;
+  });
+}
+
+int ovl_stencil_set_shape(const ovl_geom* g, ovl_prec prec, int compress12, int nextra, int nrhs, const int* shape) {
+  return guard([&] {
+    OVL_REQUIRE(g && shape, OVL_E_ARG, "null argument");
+    check_prec(prec);
+    check_nrhs(nrhs);
+    const int kr = shape[0], bs = shape[1], pipe = shape[2], rin = shape[3], tm = shape[4];
+    OVL_REQUIRE(nextra >= 0 && nextra <= 3, OVL_E_ARG, "nextra must be 0..3");
+    OVL_REQUIRE(bs == 32 || bs == 64 || bs == 128 || bs == 256, OVL_E_ARG, "bs must be 32, 64, 128 or 256");
+    OVL_REQUIRE(rin == 0 || rin == 1, OVL_E_ARG, "rin must be 0 or 1");
+    OVL_REQUIRE(tm == 0 || tm == 1, OVL_E_ARG, "tm must be 0 or 1");
+    if (pipe) {
+      OVL_REQUIRE(kr == 1 && rin == 0 && pipe >= 2 && pipe <= 4, OVL_E_ARG,
+                  "pipelined shapes need kr = 1, rin = 0, depth 2..4");
+    } else {
+      OVL_REQUIRE(kr >= 1 && kr <= (prec == OVL_F64 ? 2 : 4) && nrhs % kr == 0, OVL_E_ARG,
+                  "kr must divide nrhs (kr <= 4, <= 2 for FP64)");
+      OVL_REQUIRE(!rin || bs * (nrhs / kr) <= 512, OVL_E_ARG, "rin shapes need bs * nrhs / kr <= 512");
+    }
+    for (int npar = 1; npar <= 2; ++npar)
+      force_shape(prec, compress12 ? 12 : 18, nextra, nrhs, npar, g->geo.Nh, shape);
+    return OVL_OK;
+  });
+}
+
+int ovl_stencil_timer(int mode) {
+  return guard([&] {
+    OVL_REQUIRE(mode >= 0 && mode <= 2, OVL_E_ARG, "mode must be 0, 1 or 2");
+    stencil_timer(mode);
+    return OVL_OK;
+  });
+}
+
+int ovl_stencil_timer_read(ovl_prec prec, int compress12, int nextra, int nrhs, int64_t* launches, double* total_ms) {
+  return guard([&] {
+    OVL_REQUIRE(launches && total_ms, OVL_E_ARG, "null argument");
+    check_prec(prec);
+    stencil_timer_read(prec, compress12 ? 12 : 18, nextra, nrhs, launches, total_ms);
     return OVL_OK;
   });
 }

@@ -18,6 +18,8 @@
 #include <string>
 #include <vector>
 
+#include <type_traits>
+
 #include "ovl.h"
 
 namespace ovl {
@@ -114,12 +116,15 @@ struct bf16_t {
 __host__ __device__ inline float bf16_to_float(uint16_t b) {
   return __builtin_bit_cast(float, static_cast<uint32_t>(b) << 16);
 }
-// Round to nearest even; NaN stays a (quiet) NaN.
+// Round to nearest even; NaN stays a (quiet) NaN.  Written without a branch:
+// a data-dependent branch per stored element splits the stencil kernels into
+// many basic blocks and the register allocator then keeps every loaded
+// neighbour alive across them (256 VGPRs and spills instead of ~80).
 __host__ __device__ inline uint16_t float_to_bf16(float f) {
-  uint32_t u = __builtin_bit_cast(uint32_t, f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return static_cast<uint16_t>((u >> 16) | 0x40);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return static_cast<uint16_t>(u >> 16);
+  const uint32_t u = __builtin_bit_cast(uint32_t, f);
+  const uint32_t rounded = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+  const uint32_t quiet_nan = (u >> 16) | 0x40u;
+  return static_cast<uint16_t>(((u & 0x7fffffffu) > 0x7f800000u) ? quiet_nan : rounded);
 }
 
 template <int P>
@@ -232,6 +237,28 @@ struct SpinorIO {
   }
 };
 
+// Raw (still encoded) spinor: its 16-byte blocks, for loads issued ahead of
+// the arithmetic that consumes them.
+template <int P>
+struct SpinorRaw {
+  uint4 b[12 / Prec<P>::cpb];
+};
+
+template <int P>
+__device__ inline void spinor_load_raw(const void* base, int p, int h, int Nh, SpinorRaw<P>& r) {
+  constexpr int nb = 12 / Prec<P>::cpb;
+  const char* b = static_cast<const char*>(base) + (static_cast<size_t>(p) * nb * Nh + h) * 16;
+#pragma unroll
+  for (int j = 0; j < nb; ++j) r.b[j] = *reinterpret_cast<const uint4*>(b + static_cast<size_t>(j) * Nh * 16);
+}
+
+template <int P>
+__device__ inline void spinor_unpack(const SpinorRaw<P>& r, Cx<typename Prec<P>::real>* s) {
+  constexpr int cpb = Prec<P>::cpb;
+#pragma unroll
+  for (int j = 0; j < 12 / cpb; ++j) Block<P>::load(&r.b[j], s + j * cpb);
+}
+
 // ------------------------------------------------------------ link formats
 // Layout [mu][parity][K][Nh] of E-byte elements.  R = 18 or 12 reals.
 //   F64: E = 16 (one complex);            K = 9 or 6
@@ -330,6 +357,36 @@ struct ScalarIO<OVL_BF16> {
   }
 };
 
+template <typename T>
+__host__ __device__ inline T ffma(T a, T b, T c) {
+  if constexpr (std::is_same_v<T, double>)
+    return __builtin_fma(a, b, c);
+  else
+    return __builtin_fmaf(a, b, c);
+}
+
+// Third row of an SU(3) matrix from the first two: row2 = conj(row0 x row1).
+// Element c is conj(x y - z w) with x = r0[a], y = r1[b], z = r0[b],
+// w = r1[a] and (a, b) the two columns after c (cyclically), four FMAs for
+// each real part.
+template <typename T>
+__device__ inline void reconstruct_row2(Cx<T> (*u)[3]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const int a = (c + 1) % 3, b = (c + 2) % 3;
+    const Cx<T> x = u[0][a], y = u[1][b], z = u[0][b], w = u[1][a];
+    T re = x.re * y.re;
+    re = ffma(-x.im, y.im, re);
+    re = ffma(-z.re, w.re, re);
+    re = ffma(z.im, w.im, re);
+    T im = z.re * w.im;  // imaginary part of the conjugate
+    im = ffma(z.im, w.re, im);
+    im = ffma(-x.re, y.im, im);
+    im = ffma(-x.im, y.re, im);
+    u[2][c] = {re, im};
+  }
+}
+
 // Loads the 3x3 link matrix u[row][col] of direction mu at (p, h).
 template <int P, int R>
 struct LinkIO {
@@ -352,13 +409,63 @@ struct LinkIO {
 #pragma unroll
       for (int k = 6; k < 9; ++k) u[2][k - 6] = c[k];
     } else {
-      // row2 = conj(row0 x row1)
-      u[2][0] = conj(u[0][1] * u[1][2] - u[0][2] * u[1][1]);
-      u[2][1] = conj(u[0][2] * u[1][0] - u[0][0] * u[1][2]);
-      u[2][2] = conj(u[0][0] * u[1][1] - u[0][1] * u[1][0]);
+      reconstruct_row2(u);
     }
   }
 };
+
+// Raw (still encoded) link: K elements of E bytes as 32-bit words.
+template <int P, int R>
+struct LinkRaw {
+  using F = LinkFmt<P, R>;
+  uint32_t w[F::K * F::E / 4];
+};
+
+template <int P, int R>
+__device__ inline void link_load_raw(const void* links, int mu, int p, int h, int Nh, LinkRaw<P, R>& r) {
+  using F = LinkFmt<P, R>;
+  const char* b = static_cast<const char*>(links) + ((static_cast<size_t>(mu) * 2 + p) * F::K * Nh + h) * F::E;
+#pragma unroll
+  for (int k = 0; k < F::K; ++k) {
+    const char* a = b + static_cast<size_t>(k) * Nh * F::E;
+    if constexpr (F::E == 16) {
+      const uint4 v = *reinterpret_cast<const uint4*>(a);
+      r.w[4 * k] = v.x;
+      r.w[4 * k + 1] = v.y;
+      r.w[4 * k + 2] = v.z;
+      r.w[4 * k + 3] = v.w;
+    } else if constexpr (F::E == 8) {
+      const uint2 v = *reinterpret_cast<const uint2*>(a);
+      r.w[2 * k] = v.x;
+      r.w[2 * k + 1] = v.y;
+    } else {
+      r.w[k] = *reinterpret_cast<const uint32_t*>(a);
+    }
+  }
+}
+
+template <int P, int R>
+__device__ inline void link_unpack(const LinkRaw<P, R>& r, Cx<typename Prec<P>::real> (*u)[3]) {
+  using F = LinkFmt<P, R>;
+  using real = typename Prec<P>::real;
+  const char* b = reinterpret_cast<const char*>(r.w);
+  Cx<real> c[9];
+  if constexpr (F::cpe == 1) {
+#pragma unroll
+    for (int k = 0; k < F::ncx; ++k) c[k] = ScalarIO<P>::load1(b + k * F::E);
+  } else {
+#pragma unroll
+    for (int k = 0; k < F::K; ++k) ScalarIO<P>::load2(b + k * F::E, c + 2 * k);
+  }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) u[k / 3][k % 3] = c[k];
+  if constexpr (R == 18) {
+#pragma unroll
+    for (int k = 6; k < 9; ++k) u[2][k - 6] = c[k];
+  } else {
+    reconstruct_row2(u);
+  }
+}
 
 // ------------------------------------------------------------ geometry
 struct Geo {

@@ -25,15 +25,21 @@ struct StencilArgs {
   int g5;
   int par0, npar;
   size_t vstride;
+  // 1: consecutive blocks of a parity walk t at a fixed tile of the (x, y, z)
+  // half-slice, so t-neighbours are reused from cache; 0: blocks follow h
+  int tmaj = 0;
 };
+
 
 void launch_stencil(const StencilArgs& A, int prec, int recon, int nrhs, hipStream_t s);
 // Stencil shape selection: mode 1 autotunes (default), 0 uses the static
 // default (largest KR <= 4, <= 2 for FP64, dividing nrhs; 256 threads).
 // Changing the mode clears the tuned table.
 void set_tune_mode(int mode);
-// Tuned shape of a configuration, if any: returns 1 and fills kr, bs.
-int stencil_shape(int prec, int recon, int nv, int nrhs, int npar, int nh, int* kr, int* bs);
+// Tuned shape of a configuration, if any: returns 1 and fills kr, bs, pipe.
+int stencil_shape(int prec, int recon, int nv, int nrhs, int npar, int nh, int* shape5);
+// Pins the shape of a configuration (tests, measurements).
+void force_shape(int prec, int recon, int nv, int nrhs, int npar, int nh, const int* shape5);
 
 // Representation of the links that operators at spinor precision prec use.
 const void* gauge_links(const ovl_gauge* u, int prec, int* recon);
@@ -92,5 +98,8 @@ void net_apply(const ovl_net* net, const ovl_gauge* u, const void* in, void* out
 
 // Counters of stencil work issued from the host (not counting graph replays).
 void count_stencil(int nrhs);
+// Launch timer: mode 1 clears and enables, 0 disables, 2 clears.
+void stencil_timer(int mode);
+void stencil_timer_read(int prec, int recon, int nv, int nrhs, int64_t* launches, double* ms);
 
 }  // namespace ovl

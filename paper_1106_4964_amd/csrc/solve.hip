@@ -103,18 +103,20 @@ __global__ void beta_kernel(int R, Scalars* S) {
 struct Solver {
   const ovl_gauge* u;
   double rho, m;
-  const ovl_sign* sg;
+  const ovl_sign* sg;      // outer (FP64 true residual)
+  const ovl_sign* sg_in;   // inner operator
   const ovl_lowmodes* lm;
   int R, P;
   hipStream_t s;
   size_t v64, vP, nsites;
   ovl_solve_stats* st;
-  int64_t per_sign_dw;
+  int64_t per_sign_dw, per_sign_dw_in;
 
-  void dm(void* out, const void* in, int prec, int dagger) {
-    overlap_apply(out, in, u, rho, m, sg, lm, dagger ? 2 : 1, prec, R, s);
+  // inner = true: the inner operator (relaxed sign), else the FP64 one
+  void dm(void* out, const void* in, int prec, int dagger, bool inner) {
+    overlap_apply(out, in, u, rho, m, inner ? sg_in : sg, lm, dagger ? 2 : 1, prec, R, s);
     st->sign_applies += R;
-    st->dslash_applies += R * per_sign_dw;
+    st->dslash_applies += R * (inner ? per_sign_dw_in : per_sign_dw);
   }
   void norm2(const void* x, int prec, double* dev_out, Scalars* S) {
     blas_norm2(prec, (prec == OVL_F64 ? v64 : vP) / 16, x, R, prec == OVL_F64 ? v64 : vP, S->dot_tmp, s);
@@ -152,6 +154,9 @@ int cg_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, doub
   S.v64 = spinor_vec_bytes(&u->geom, OVL_F64);
   S.vP = spinor_vec_bytes(&u->geom, P);
   S.per_sign_dw = 2 * (static_cast<int64_t>(sg->c.size()) - 1) + 1;
+  S.sg_in = (o && o->inner_sign) ? o->inner_sign : sg;
+  OVL_REQUIRE(S.sg_in->lam_max == sg->lam_max, OVL_E_ARG, "inner_sign must share lam_max with sign");
+  S.per_sign_dw_in = 2 * (static_cast<int64_t>(S.sg_in->c.size()) - 1) + 1;
   int recon = 0;
   (void)gauge_links(u, P, &recon);  // the inner precision must have links
 
@@ -210,12 +215,12 @@ int cg_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, doub
       S.norm2(p.p, P, dS->pp, dS);
       hipLaunchKernelGGL(alpha_kernel, dim3(1), dim3(64), 0, s, R, dS);
       blas_axpby(P, p.p, dS->alpha, OVL_F64, e64.p, dS->one, S.nsites, R, s);
-      S.dm(q.p, p.p, P, 0);
+      S.dm(q.p, p.p, P, 0, true);
       if (harvest && !capturing) harvest_pairs();
       blas_axpby(P, q.p, dS->malpha, P, rin.p, dS->one, S.nsites, R, s);
       S.norm2(rin.p, P, dS->rrn, dS);
       hipLaunchKernelGGL(beta_kernel, dim3(1), dim3(64), 0, s, R, dS);
-      S.dm(t.p, rin.p, P, 1);
+      S.dm(t.p, rin.p, P, 1, true);
       blas_axpby(P, t.p, dS->one, P, p.p, dS->beta, S.nsites, R, s);
     };
 
@@ -224,7 +229,7 @@ int cg_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, doub
     st->restarts = 0;
     for (;;) {
       // true residual r = b - D(m) x in FP64
-      S.dm(tmp64.p, x, OVL_F64, 0);
+      S.dm(tmp64.p, x, OVL_F64, 0, false);
       blas_axpby(OVL_F64, b, dS->one, OVL_F64, r64.p, nullptr, S.nsites, R, s);
       blas_axpby(OVL_F64, tmp64.p, dS->mone, OVL_F64, r64.p, dS->one, S.nsites, R, s);
       S.norm2(r64.p, OVL_F64, dS->rrn, dS);
@@ -272,7 +277,7 @@ int cg_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, doub
       blas_axpby(OVL_F64, r64.p, dS->iscale, P, rin.p, nullptr, S.nsites, R, s);
       blas_zero(e64.p, S.v64 * R, s);
       S.norm2(rin.p, P, dS->rr, dS);
-      S.dm(p.p, rin.p, P, 1);
+      S.dm(p.p, rin.p, P, 1, true);
 
       int inner = 0;
       for (;;) {
@@ -292,7 +297,7 @@ int cg_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, doub
           OVL_HIP(hipGraphLaunch(gexec, s));
           step = opt.graph_chunk;
           st->sign_applies += static_cast<int64_t>(2) * R * step;
-          st->dslash_applies += static_cast<int64_t>(2) * R * step * S.per_sign_dw;
+          st->dslash_applies += static_cast<int64_t>(2) * R * step * S.per_sign_dw_in;
         } else {
           const int nrun = (opt.graph_chunk > 0 || harvest) ? 1 : check_every;
           for (int k = 0; k < nrun; ++k) body();
@@ -358,6 +363,9 @@ int fgcr_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, do
   const size_t N = static_cast<size_t>(g->N);
   const size_t v64 = spinor_vec_bytes(g, OVL_F64), vP = spinor_vec_bytes(g, P), v32 = spinor_vec_bytes(g, OVL_F32);
   const int64_t per_sign_dw = 2 * (static_cast<int64_t>(sg->c.size()) - 1) + 1;
+  const ovl_sign* sg_in = (o && o->inner_sign) ? o->inner_sign : sg;
+  OVL_REQUIRE(sg_in->lam_max == sg->lam_max, OVL_E_ARG, "inner_sign must share lam_max with sign");
+  const int64_t per_sign_dw_in = 2 * (static_cast<int64_t>(sg_in->c.size()) - 1) + 1;
 
   hipStream_t s;
   OVL_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
@@ -386,10 +394,10 @@ int fgcr_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, do
       out.resize(nr);
       for (int r = 0; r < nr; ++r) out[r] = h[2 * r];
     };
-    auto dm = [&](void* out, const void* in, int prec) {
-      overlap_apply(out, in, u, rho, m, sg, lm, 1, prec, R, s);
+    auto dm = [&](void* out, const void* in, int prec, bool inner) {
+      overlap_apply(out, in, u, rho, m, inner ? sg_in : sg, lm, 1, prec, R, s);
       st->sign_applies += R;
-      st->dslash_applies += R * per_sign_dw;
+      st->dslash_applies += R * (inner ? per_sign_dw_in : per_sign_dw);
     };
     auto vec = [&](void* base, size_t vs, int i) { return static_cast<char*>(base) + static_cast<size_t>(i) * vs; };
     // y_r += a x_r for one rhs (host scalar)
@@ -416,7 +424,7 @@ int fgcr_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, do
       mones[2 * r] = -1.0;
     }
     for (;;) {
-      dm(tmp64.p, x, OVL_F64);
+      dm(tmp64.p, x, OVL_F64, false);
       std::vector<double> c(4 * OVL_MAX_RHS, 0.0);
       for (int r = 0; r < R; ++r) {
         c[2 * r] = 1.0;
@@ -475,7 +483,7 @@ int fgcr_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, do
           } else {
             blas_convert(OVL_F64, rin.p, P, zP.p, N, R, s);
           }
-          dm(wP.p, zP.p, P);
+          dm(wP.p, zP.p, P, true);
           blas_convert(P, wP.p, OVL_F64, w64.p, N, R, s);
           blas_convert(P, zP.p, OVL_F64, z64.p, N, R, s);
           ++its;
@@ -567,6 +575,7 @@ int fgcr_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, do
     co.graph_chunk = o ? o->graph_chunk : 0;
     co.check_every = 1;
     co.max_restarts = max_restarts;
+    co.inner_sign = o ? o->inner_sign : nullptr;
     const int its0 = st->iterations;
     const int64_t sa = st->sign_applies, da = st->dslash_applies;
     rc = cg_solve(x, b, R, u, rho, m, sg, lm, tol, std::max(0, maxiter - its0), &co, &cs, us);

@@ -79,6 +79,7 @@ class SolveOpts(ctypes.Structure):
         ("harvest_x", ctypes.c_void_p),
         ("harvest_b", ctypes.c_void_p),
         ("harvest_cap", ctypes.c_int),
+        ("inner_sign", ctypes.c_void_p),
     ]
 
 
@@ -147,7 +148,10 @@ _SIGS = {
     "ovl_propagator": (P, P, P, D, P, P, I, I, ST),
     "ovl_counters": (P, P, I),
     "ovl_stencil_tune": (I,),
-    "ovl_stencil_shape": (P, I, I, I, I, P, P),
+    "ovl_stencil_timer": (I,),
+    "ovl_stencil_timer_read": (I, I, I, I, P, P),
+    "ovl_stencil_shape": (P, I, I, I, I, P),
+    "ovl_stencil_set_shape": (P, I, I, I, I, P),
     "ovl_hw_bound": (P, D, P, I, P, P, P, ST),
     "ovl_hw_eigs": (P, D, I, I, P, P, D, D, I, I, P, ST),
     "ovl_host_heev": (I, P, P, P),
@@ -357,3 +361,22 @@ class Net:
         if getattr(self, "handle", None) is not None and self.handle.value:
             lib.ovl_net_destroy(self.handle)
             self.handle = None
+
+
+def stencil_shape(geom, prec, compress12, nextra, nrhs):
+    """Tuned shape (kr, bs, pipe, rin, tm) of a stencil configuration, zeros if untuned."""
+    sh = (ctypes.c_int * 5)()
+    ovl_stencil_shape(geom, prec, int(compress12), nextra, nrhs, sh)
+    return tuple(sh)
+
+
+def stencil_set_shape(geom, prec, compress12, nextra, nrhs, shape):
+    sh = (ctypes.c_int * 5)(*shape)
+    ovl_stencil_set_shape(geom, prec, int(compress12), nextra, nrhs, sh)
+
+
+def stencil_timer_read(prec, compress12, nextra, nrhs):
+    """(launches, summed milliseconds) of one stencil configuration since the last clear."""
+    n, ms = ctypes.c_int64(), ctypes.c_double()
+    ovl_stencil_timer_read(prec, int(compress12), nextra, nrhs, ctypes.byref(n), ctypes.byref(ms))
+    return n.value, ms.value

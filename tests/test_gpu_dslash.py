@@ -163,10 +163,59 @@ def test_every_vectors_per_thread_shape(prec):
         ovl.ovl_stencil_tune(1)
     out = gu.empty_field(g, prec, 12)
     ovl.ovl_dslash(out, inp, gauge, -0.3, 2, prec, 12, None)
-    kr, bs = ctypes.c_int(), ctypes.c_int()
-    ovl.ovl_stencil_shape(g, prec, 0 if prec == ovl.OVL_F64 else 1, 0, 12, ctypes.byref(kr), ctypes.byref(bs))
-    assert kr.value in (1, 2, 3, 4) and bs.value in (128, 256)
+    kr, bs, pipe, rin, tm = ovl.stencil_shape(g, prec, prec != ovl.OVL_F64, 0, 12)
+    assert kr in (1, 2, 3, 4) and bs in (32, 64, 128, 256) and pipe in (0, 2, 3, 4) and rin in (0, 1)
+    assert tm in (0, 1)
     got = gu.unpack(g, out, prec, 12)
     assert gu.max_rel_err(got, want) <= 2 * gu.UNIT_ROUNDOFF[prec]
     ref = dirac.wilson_dslash(lat, U, psi[5], -0.3)
     assert gu.rel_err(got[5], ref) < 16 * gu.UNIT_ROUNDOFF[prec] + 4e-7
+
+
+def _shape_candidates(prec, nrhs):
+    kmax = 2 if prec == ovl.OVL_F64 else 4
+    out = []
+    for tm in (0, 1):
+        for kr in range(1, kmax + 1):
+            if nrhs % kr:
+                continue
+            out += [(kr, 128, 0, 0, tm), (kr, 256, 0, 0, tm)]
+            if nrhs > kr:
+                out += [(kr, bs, 0, 1, tm) for bs in (32, 64) if bs * (nrhs // kr) <= 512]
+        for dep in ((2,) if prec == ovl.OVL_F64 else (2, 3, 4)):
+            out += [(1, 128, dep, 0, tm), (1, 256, dep, 0, tm)]
+    return out
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_every_pinned_shape(prec):
+    """Every shape the tuner may pick (vectors per thread, side-by-side groups,
+    pipelined loads), pinned in turn on a 12-rhs H_w batch, matches the same
+    batch under the static default shape."""
+    dims = (6, 6, 6, 10)
+    U = si.gauge_field(dims, 0.25, 8)
+    g = ovl.Geometry(dims)
+    c12 = prec != ovl.OVL_F64
+    gauge = gu.make_gauge(g, U, [(prec, 1)] if c12 else [])
+    psi = np.stack([si.gaussian_spinor(dims, 500 + r) for r in range(12)])
+    inp = gu.pack(g, psi, prec, 12)
+    ovl.ovl_stencil_tune(0)
+    try:
+        ref = gu.empty_field(g, prec, 12)
+        ovl.ovl_hw_apply(ref, inp, gauge, 1.4, prec, 12, None)
+        want = gu.unpack(g, ref, prec, 12)
+        for shape in _shape_candidates(prec, 12):
+            ovl.stencil_set_shape(g, prec, c12, 0, 12, shape)
+            assert ovl.stencil_shape(g, prec, c12, 0, 12) == shape
+            out = gu.empty_field(g, prec, 12)
+            ovl.ovl_hw_apply(out, inp, gauge, 1.4, prec, 12, None)
+            got = gu.unpack(g, out, prec, 12)
+            assert gu.max_rel_err(got, want) <= 2 * gu.UNIT_ROUNDOFF[prec], shape
+        # unsupported block size, kr, block above 512 threads, pipelined kr > 1,
+        # pipeline depth, rin flag, tm flag
+        for bad in [(1, 96, 0, 0, 0), (5, 128, 0, 0, 0), (1, 64, 0, 1, 0), (2, 128, 2, 0, 0), (1, 128, 5, 0, 0),
+                    (1, 128, 0, 2, 0), (1, 128, 0, 0, 2)]:
+            with pytest.raises(ovl.OvlError):
+                ovl.stencil_set_shape(g, prec, c12, 0, 12, bad)
+    finally:
+        ovl.ovl_stencil_tune(1)

@@ -154,6 +154,35 @@ def test_cg_12_point_sources_with_lowmodes(c1, c1_lowmodes, prec, graph):
         assert st.true_residual[r] <= 1e-10
 
 
+@pytest.mark.parametrize("prec", [ovl.OVL_F32, ovl.OVL_F16])
+def test_cg_relaxed_inner_sign(c1, c1_lowmodes, prec):
+    """A lower-order sign function (delta 1e-5) inside the low-precision
+    inner solves; the FP64 outer residual, computed with the full-accuracy
+    sign, still reaches 1e-10, judged by the oracle's operator."""
+    V, lam = c1_lowmodes
+    g = ovl.Geometry(c1["dims"])
+    gauge = gu.make_gauge(g, c1["U"], [(prec, 1)])
+    lm = ovl.LowModes(g, gu.pack(g, V, ovl.OVL_F64, len(V)), lam)
+    s = ovl.Sign(abs(lam[-1]), c1["hi"], delta=1e-12)
+    s_in = ovl.Sign(abs(lam[-1]), c1["hi"], delta=1e-5)
+    assert s_in.n < s.n
+    so = sign.SignApprox(lam_max=c1["hi"], eps=s.eps, coeffs=s.coeffs())
+    b = si.point_sources(c1["dims"])[[0, 5, 10]]
+    R = b.shape[0]
+    bd = gu.pack(g, b, ovl.OVL_F64, R)
+    x = gu.pack(g, np.zeros_like(b), ovl.OVL_F64, R)
+    inner_tol = 1e-4 if prec == ovl.OVL_F32 else 1e-2
+    opts = ovl.SolveOpts(prec, inner_tol, 0, 1, 50, None, None, 0, s_in.handle.value)
+    st = ovl.SolveStats()
+    rc = ovl.ovl_cg_solve(x, bd, R, gauge, RHO, 0.01, s, lm, 1e-10, 5000, opts, st, None)
+    assert rc == 0, list(st.true_residual)
+    xs = gu.unpack(g, x, ovl.OVL_F64, R)
+    print("relaxed inner sign n=%d/%d: iterations %d restarts %d" % (s_in.n, s.n, st.iterations, st.restarts))
+    for r in range(R):
+        res = b[r] - sign.overlap_apply(c1["lat"], c1["U"], xs[r], RHO, 0.01, so, V, lam)
+        assert np.linalg.norm(res) / np.linalg.norm(b[r]) <= 1.05e-10
+
+
 def test_cg_batch_equals_single(c1, c1_lowmodes):
     V, lam = c1_lowmodes
     g = ovl.Geometry(c1["dims"])
