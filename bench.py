@@ -37,6 +37,15 @@ sys.path.insert(0, ROOT)
 METRIC = "dslash GB/s + D_ov applies/s at 24^3x64; CG time to 1e-10 vs plain FP64"
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch from two rocprofv3 counter passes (FETCH_SIZE x 2.0 +
+# WRITE_SIZE x 1.0, factors from a plain 1 GiB copy), keyed by the F16 12-rhs
+# stencil configuration: (extra epilogue vectors, tuned shape kr, bs, pipe,
+# rin, tm).  Summary and commands: profiles/stencil_f16_12rhs_24x24x24x64_counters.md
+PROFILED_TRAFFIC = {
+    (3, (1, 256, 0, 0, 0)): 4811612160,
+    (0, (2, 128, 0, 0, 0)): 3306946560,
+}
+
 
 def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
@@ -156,6 +165,18 @@ def kernels_mode(dims, prec_name):
             ovl.ovl_hw_apply(y, x, gauge, 1.5, p, nrhs, None)
         torch.cuda.synchronize()
         log("stencil %s: shape (kr, bs, pipe, rin, tm) = %s" % (name, ovl.stencil_shape(g, p, p != ovl.OVL_F64, 0, nrhs)))
+    # the Clenshaw recurrence of the sign function on 12 rhs: its steps are
+    # the stencil with 0 and with 3 extra epilogue vectors
+    x = torch.empty(g.spinor_bytes(prec, 12), dtype=torch.uint8, device=dev)
+    ovl.ovl_convert(g, b64, ovl.OVL_F64, x, prec, 12, None)
+    y = torch.empty_like(x)
+    sgn = ovl.Sign(0.1, 6.4, n=6)
+    for _ in range(6):  # the first call tunes; the last five run the tuned shapes
+        ovl.ovl_sign_apply(y, x, gauge, 1.5, sgn, None, prec, 12, None)
+    torch.cuda.synchronize()
+    for nv in (0, 3):
+        log("clenshaw stencil %s 12 rhs, %d extra vectors: shape (kr, bs, pipe, rin, tm) = %s"
+            % (prec_name, nv, ovl.stencil_shape(g, prec, 1, nv, 12)))
 
 
 # ---------------------------------------------------------------------------
@@ -302,18 +323,22 @@ def main():
     dom_us = 1e3 * ms_dom / n_dom
     dom_bytes = model_bytes(prec, 12, R, dom_nv)
     dom_gbs = dom_bytes / (dom_us * 1e-6) / 1e9
+    dom_shape = tuple(ovl.stencil_shape(g, prec, 1, dom_nv, R))
+    profiled = dims == (24, 24, 24, 64) and R == 12 and args.prec == "f16"
+    traffic = PROFILED_TRAFFIC.get((dom_nv, dom_shape)) if profiled else None
     roofline = {
         "bound": "hbm",
         "achieved": round(dom_gbs, 1),
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(dom_gbs / HBM_PEAK_GBS, 4),
-        "traffic": None,
+        "traffic": traffic,
         "kernel": "stencil_kernel<F16, 12-real links, %d extra vectors>, %d rhs, %s" % (dom_nv, R, "x".join(map(str, dims))),
         "bytes_per_launch": dom_bytes,
         "avg_launch_us": round(dom_us, 2),
         "launches": n_dom,
         "share_of_step": round(ms_dom / (1e3 * t_steps), 4),
+        "shape": list(dom_shape),
     }
 
     # ----------------------------------------------------------------- CG

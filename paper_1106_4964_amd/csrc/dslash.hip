@@ -9,6 +9,7 @@
 // The epilogue forms  G(a*in + b*hop) + sum_j c_j G_j(v_j)  at the output
 // site, which covers D_w(m), H_w = gamma5 D_w(-rho), and the Clenshaw
 // update of the polynomial sign function (Sec. V) in one pass.
+#include <algorithm>
 #include <atomic>
 #include <cstdlib>
 #include <tuple>
@@ -463,21 +464,31 @@ Shape pick_shape(const StencilArgs& A, int prec, int recon, int nrhs, hipStream_
   hipEvent_t e0, e1;
   OVL_HIP(hipEventCreate(&e0));
   OVL_HIP(hipEventCreate(&e1));
-  Shape best = def;
-  float best_ms = 1e30f;
-  for (const Shape& c : candidates(prec, nrhs)) {
-    launch_shape(T, prec, recon, nrhs, c, s);  // warm-up
-    OVL_HIP(hipEventRecord(e0, s));
-    for (int r = 0; r < 3; ++r) launch_shape(T, prec, recon, nrhs, c, s);
-    OVL_HIP(hipEventRecord(e1, s));
-    OVL_HIP(hipEventSynchronize(e1));
-    float ms = 0.f;
-    OVL_HIP(hipEventElapsedTime(&ms, e0, e1));
-    if (ms < best_ms) {
-      best_ms = ms;
-      best = c;
+  // two rounds over the candidates, each timed over 3 launches after a
+  // warm-up launch; a candidate's time is its better round.  The first
+  // candidate (in list order) within 2% of the fastest wins, so that shapes
+  // that time alike give the same choice from run to run.
+  const std::vector<Shape> cand = candidates(prec, nrhs);
+  std::vector<float> best_ms(cand.size(), 1e30f);
+  for (int round = 0; round < 2; ++round)
+    for (size_t i = 0; i < cand.size(); ++i) {
+      launch_shape(T, prec, recon, nrhs, cand[i], s);  // warm-up
+      OVL_HIP(hipEventRecord(e0, s));
+      for (int r = 0; r < 3; ++r) launch_shape(T, prec, recon, nrhs, cand[i], s);
+      OVL_HIP(hipEventRecord(e1, s));
+      OVL_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      OVL_HIP(hipEventElapsedTime(&ms, e0, e1));
+      best_ms[i] = std::min(best_ms[i], ms);
     }
-  }
+  float fastest = 1e30f;
+  for (float t : best_ms) fastest = std::min(fastest, t);
+  Shape best = def;
+  for (size_t i = 0; i < cand.size(); ++i)
+    if (best_ms[i] <= 1.02f * fastest) {
+      best = cand[i];
+      break;
+    }
   OVL_HIP(hipEventDestroy(e0));
   OVL_HIP(hipEventDestroy(e1));
   std::lock_guard<std::mutex> lk(g_tune_mu);
