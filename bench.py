@@ -69,9 +69,12 @@ def parse():
     ap.add_argument("--fp64-cg-rhs", type=int, default=1,
                     help="rhs of the plain FP64 CG comparison (time scaled to 12); 0 = skip")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--mode", choices=["full", "kernels"], default="full",
+    ap.add_argument("--mode", choices=["full", "kernels", "learned"], default="full",
                     help="kernels: only a 1 GiB calibration copy and the stencil configurations "
-                         "(for rocprofv3 counter passes)")
+                         "(for rocprofv3 counter passes); learned: train the PTC preconditioner on "
+                         "16^3x32 fields and compare FGCR(net), FGCR(M=1) and CG on the --dims field")
+    ap.add_argument("--pairs", type=int, default=2000, help="learned mode: training pairs (four fields)")
+    ap.add_argument("--restart", type=int, default=16, help="learned mode: FGCR restart length")
     ap.add_argument("--cpu-only", action="store_true", help=argparse.SUPPRESS)
     return ap.parse_args()
 
@@ -180,6 +183,147 @@ def kernels_mode(dims, prec_name):
 
 
 # ---------------------------------------------------------------------------
+def spectral_setup(ovl, g, gauge, dims, rho, ell, delta, seed_base, tol=1e-12):
+    """Lanczos bound on |H_w|, the ell lowest |lambda| eigenpairs of H_w and
+    the sign function for sqrt(eps) = |lambda_ell| / lambda_max."""
+    import numpy as np
+    import torch
+
+    import synth_inputs as si
+
+    dev = torch.device("cuda:0")
+    log("Lanczos bound")
+    v0 = torch.empty(g.spinor_bytes(ovl.OVL_F64), dtype=torch.uint8, device=dev)
+    ovl.ovl_pack_spinor(g, torch.from_numpy(si.gaussian_spinor(dims, 17)[None]).to(dev), v0, ovl.OVL_F64, 1, None)
+    lam = ctypes.c_double()
+    ovl.ovl_hw_bound(gauge, rho, v0, 60, ctypes.byref(lam), None, None, None)
+    lam_max = lam.value * (1 + 1e-6)
+    del v0
+    m = ell + max(12, ell // 4)
+    log("eigensolver: %d of %d vectors" % (ell, m))
+    V = torch.empty(g.spinor_bytes(ovl.OVL_F64, m), dtype=torch.uint8, device=dev)
+    for i in range(0, m, 8):
+        k = min(8, m - i)
+        blk = np.stack([si.gaussian_spinor(dims, seed_base + i + j) for j in range(k)])
+        ovl.ovl_pack_spinor(g, torch.from_numpy(blk).to(dev),
+                            V[i * g.spinor_bytes(ovl.OVL_F64):], ovl.OVL_F64, k, None)
+    lams = np.zeros(ell)
+    est = ovl.EigStats()
+    rc = ovl.ovl_hw_eigs(gauge, rho, ell, m, V, lams, lam_max, tol, 60, 40, ctypes.byref(est), None)
+    log("eigensolver rc %d: %d passes, %d H_w applies, max residual %.2e, %.1f s, |lambda_l| = %.4f"
+        % (rc, est.iterations, est.hw_applies, est.max_residual, est.seconds, abs(lams[-1])))
+    Vk = V[: ell * g.spinor_bytes(ovl.OVL_F64)]
+    lm = ovl.LowModes(g, Vk, lams)
+    sgn = ovl.Sign(abs(lams[-1]), lam_max, delta=delta)
+    log("sign: n = %d, sqrt(eps) = %.4f, delta = %.2e" % (sgn.n, math.sqrt(sgn.eps), sgn.delta))
+    return lam_max, lams, V, lm, sgn
+
+
+# ---------------------------------------------------------------------------
+def learned_mode(args, dims):
+    """The learned preconditioner at scale: a 1-4-1 PTC network trained on
+    (b, x) pairs from four 16^3x32 fields, then the right preconditioner of
+    FGCR for D(m) on the 24^3x64 field, against mixed CG and FGCR with M = 1."""
+    import numpy as np
+    import torch
+
+    import synth_inputs as si
+    from paper_1106_4964_amd import ovl
+
+    dev = torch.device("cuda:0")
+    rho, mass, R = 1.5, 0.01, 12
+    prec = ovl.PREC[args.prec]
+    F32, F64 = ovl.OVL_F32, ovl.OVL_F64
+    tdims = (16, 16, 16, 32)
+    pairs_per_field = args.pairs // 4
+    tg = ovl.Geometry(tdims)
+    vb = tg.spinor_bytes(F32)
+    fields = []
+    t0 = time.perf_counter()
+    for seed in (41, 42, 43, 44):
+        log("training field %s seed %d" % (tdims, seed))
+        gt = ovl.Gauge(tg, torch.from_numpy(si.gauge_field(tdims, 0.25, seed)).to(dev))
+        gt.set_repr(F32, 0)
+        _, _, Vt, lmt, st_ = spectral_setup(ovl, tg, gt, tdims, rho, 20, 1e-8, 100 * seed, tol=1e-10)
+        X = torch.empty(tg.spinor_bytes(F32, pairs_per_field), dtype=torch.uint8, device=dev)
+        B = torch.empty_like(X)
+        tmp = torch.empty(tg.spinor_bytes(F64, 12), dtype=torch.uint8, device=dev)
+        for i0 in range(0, pairs_per_field, 12):
+            k = min(12, pairs_per_field - i0)
+            blk = np.stack([si.gaussian_spinor(tdims, 10000 * seed + i0 + j) for j in range(k)])
+            ovl.ovl_pack_spinor(tg, torch.from_numpy(blk).to(dev), tmp, F64, k, None)
+            ovl.ovl_convert(tg, tmp, F64, X[i0 * vb:], F32, k, None)
+            ovl.ovl_overlap_apply(B[i0 * vb:], X[i0 * vb:], gt, rho, mass, st_, lmt, 0, F32, k, None)
+        torch.cuda.synchronize()
+        fields.append((gt, X, B, Vt, lmt, st_))
+    t_pairs = time.perf_counter() - t0
+    net_t = ovl.Net(tg, 4)
+    rng = np.random.default_rng(5)
+    w1 = 0.02 * (rng.standard_normal((9, 4, 1, 4, 4)) + 1j * rng.standard_normal((9, 4, 1, 4, 4)))
+    w2 = 0.02 * (rng.standard_normal((9, 1, 4, 4, 4)) + 1j * rng.standard_normal((9, 1, 4, 4, 4)))
+    w1[0, 0, 0] += np.eye(4)
+    w2[0, 0, 0] += np.eye(4) / rho
+    net_t.set_weights(w1, w2)
+    losses = []
+    t0 = time.perf_counter()
+    for rnd, (epochs, lr) in enumerate([(3, 1e-3), (2, 3e-4)]):
+        for (gt, X, B, _, _, _) in fields:
+            order = np.concatenate([rng.permutation(pairs_per_field) for _ in range(epochs)]).astype(np.int32)
+            hist = np.zeros(epochs)
+            ovl.ovl_net_train(net_t, gt, B, X, pairs_per_field, epochs, 8, lr, order, hist, None)
+            losses.append([round(float(v), 5) for v in hist])
+            log("training round %d: loss %s" % (rnd, losses[-1]))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    w1t, w2t = net_t.get_weights()
+    del fields, net_t
+
+    log("test field %s" % (dims,))
+    g = ovl.Geometry(dims)
+    gauge = ovl.Gauge(g, torch.from_numpy(si.gauge_field(dims, 0.25, 3)).to(dev))
+    gauge.set_repr(prec, 1)
+    gauge.set_repr(F32, 0)
+    gauge.set_repr(F32, 1)
+    lam_max, lams, V, lm, sgn = spectral_setup(ovl, g, gauge, dims, rho, args.ell, args.delta, 1000)
+    sgn_in = ovl.Sign(abs(lams[-1]), lam_max, delta=args.inner_delta)
+    net = ovl.Net(g, 4)
+    net.set_weights(w1t, w2t)
+    b64 = torch.empty(g.spinor_bytes(F64, R), dtype=torch.uint8, device=dev)
+    ovl.ovl_pack_spinor(g, torch.from_numpy(si.point_sources(dims)).to(dev), b64, F64, R, None)
+    out = {}
+    for name, M in [("cg", None), ("fgcr_net", net), ("fgcr_identity", None)]:
+        x = torch.zeros(g.spinor_bytes(F64, R), dtype=torch.uint8, device=dev)
+        opts = ovl.SolveOpts(prec, args.inner_tol, args.graph_chunk if name == "cg" else 0, 1, 60, None, None, 0,
+                             sgn_in.handle.value)
+        st = ovl.SolveStats()
+        if name == "cg":
+            rc = ovl.ovl_cg_solve(x, b64, R, gauge, rho, mass, sgn, lm, 1e-10, 20000, opts, st, None)
+        else:
+            rc = ovl.ovl_fgcr_solve(x, b64, R, gauge, rho, mass, sgn, lm, M, args.restart, 1e-10, 20000, opts, st,
+                                    None)
+        out[name] = {"rc": rc, "seconds": round(st.seconds, 2), "iterations": st.iterations,
+                     "sign_applies": st.sign_applies, "fallback_used": st.fallback_used,
+                     "max_true_residual": max(st.true_residual[r] for r in range(R))}
+        log("%s: %s" % (name, out[name]))
+    res = {
+        "metric": "learned preconditioner: FGCR(net) vs CG and FGCR(M=1), time to 1e-10 at %s" % "x".join(map(str, dims)),
+        "value": round(out["cg"]["seconds"] / out["fgcr_net"]["seconds"], 3),
+        "unit": "speedup of FGCR(net) over mixed CG",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "12 point sources, m=%g, %s storage inner, %d low modes, delta %g (inner %g), "
+                               "FGCR restart %d; net 1-4-1 trained on %d pairs from four %s fields"
+                               % (mass, args.prec, args.ell, args.delta, args.inner_delta, args.restart, args.pairs,
+                                  "x".join(map(str, tdims)))},
+        "training": {"seconds_pairs": round(t_pairs, 1), "seconds_train": round(t_train, 1), "loss": losses},
+        "solves": out,
+    }
+    print(json.dumps(res), flush=True)
+
+
+# ---------------------------------------------------------------------------
 def main():
     args = parse()
     dims = tuple(int(v) for v in args.dims.split(","))
@@ -193,6 +337,10 @@ def main():
 
     if args.mode == "kernels":
         kernels_mode(dims, args.prec)
+        return
+    if args.mode == "learned":
+        os.environ.setdefault("OVL_LOG", "1")
+        learned_mode(args, dims)
         return
     os.environ.setdefault("OVL_LOG", "1")  # solver progress lines on stderr
     import numpy as np
@@ -220,31 +368,8 @@ def main():
         ovl.ovl_pack_spinor(g, torch.from_numpy(np.ascontiguousarray(a)).to(dev), out, p, n, None)
         return out
 
-    log("Lanczos bound")
-    v0 = pack(si.gaussian_spinor(dims, 17), ovl.OVL_F64, 1)
-    lam = ctypes.c_double()
-    ovl.ovl_hw_bound(gauge, rho, v0, 60, ctypes.byref(lam), None, None, None)
-    lam_max = lam.value * (1 + 1e-6)
-    del v0
-
+    lam_max, lams, V, lm, sgn = spectral_setup(ovl, g, gauge, dims, rho, args.ell, args.delta, 1000)
     ell = args.ell
-    m = ell + max(12, ell // 4)
-    log("eigensolver: %d of %d vectors" % (ell, m))
-    V = torch.empty(g.spinor_bytes(ovl.OVL_F64, m), dtype=torch.uint8, device=dev)
-    for i in range(0, m, 8):
-        k = min(8, m - i)
-        blk = np.stack([si.gaussian_spinor(dims, 1000 + i + j) for j in range(k)])
-        ovl.ovl_pack_spinor(g, torch.from_numpy(blk).to(dev),
-                            V[i * g.spinor_bytes(ovl.OVL_F64):], ovl.OVL_F64, k, None)
-    lams = np.zeros(ell)
-    est = ovl.EigStats()
-    rc = ovl.ovl_hw_eigs(gauge, rho, ell, m, V, lams, lam_max, 1e-12, 60, 40, ctypes.byref(est), None)
-    log("eigensolver rc %d: %d passes, %d H_w applies, max residual %.2e, %.1f s, |lambda_l| = %.4f"
-        % (rc, est.iterations, est.hw_applies, est.max_residual, est.seconds, abs(lams[-1])))
-    Vk = V[: ell * g.spinor_bytes(ovl.OVL_F64)]
-    lm = ovl.LowModes(g, Vk, lams)
-    sgn = ovl.Sign(abs(lams[-1]), lam_max, delta=args.delta)
-    log("sign: n = %d, sqrt(eps) = %.4f, delta = %.2e" % (sgn.n, math.sqrt(sgn.eps), sgn.delta))
 
     b64 = pack(si.point_sources(dims), ovl.OVL_F64, R)
     bP = torch.empty(g.spinor_bytes(prec, R), dtype=torch.uint8, device=dev)
