@@ -229,6 +229,22 @@ int ovl_overlap_apply(void* out, const void* in, const ovl_gauge* u, double rho,
  *   inner_tol, so its sign function need not be more accurate than that
  *   (adaptive precision, Sec. V); the defect correction still converges to
  *   the FP64 operator built from `sign`.
+ *   opts->chiral = 1 runs each inner solve in one chirality sector
+ *   (Sec. II, eq. 3 and 8, with the chiral gamma basis of Sec. V): for
+ *   gamma5 v = s v, D(m) D(m)^dag v = (2 rho^2 + m^2/2) v
+ *   + 2 s (rho^2 - m^2/4) P_s sign(H_w) v with P_s = (1 + s gamma5)/2 when
+ *   sign^2 = 1, so CG on that sector costs one sign application per
+ *   iteration instead of two.  Each cycle picks, per rhs, the sector
+ *   holding the larger part of the residual (the only one for a point
+ *   source) and drops the other; the correction is x += D(m)^dag y, applied
+ *   in FP64 with the inner sign.  The FP64 true residual with the full
+ *   operator still decides convergence.  The sector operator equals
+ *   D D^dag only to within 2 rho^2 times the error of the sign function
+ *   (approximation and storage rounding), against a smallest eigenvalue
+ *   m^2, so a cycle gains at most about m^2 / (2 rho^2 err): it pays in FP64
+ *   with an accurate sign, not with FP16 storage at small m.  A cycle that
+ *   breaks down or does not halve the true residual switches the rest of
+ *   the solve to D D^dag.  Not with harvesting.
  *   opts may be NULL (plain FP64, no graph).  Work is done on a private
  *   stream ordered after, and before, the caller's stream s.
  * ovl_propagator: out = (1 - D/2) x (Sec. II), the propagator from a
@@ -247,6 +263,7 @@ typedef struct {
                                  (same lam_max; typically a larger delta, so
                                  a lower order); NULL = the outer one.  The
                                  FP64 true residual always uses `sign`.   */
+  int chiral;          /* CG only: 1 = inner solves in one chiral sector   */
 } ovl_solve_opts;
 
 typedef struct {

@@ -67,6 +67,27 @@ __global__ void convert_kernel(int Nh, const char* src, char* dst, size_t sstrid
 }
 
 // out = gamma5 in: complex index c = 3*spin + colour, spins 2 and 3 negated.
+// In place: keep the chirality sector[r] (+1: spins 0, 1; -1: spins 2, 3)
+// of vector r, zero the other; sector 0 leaves the vector unchanged.
+template <int P>
+__global__ void chiral_kernel(size_t n16, int Nh, char* x, size_t vstride, const int* sector) {
+  using real = typename Prec<P>::real;
+  constexpr int cpb = Prec<P>::cpb;
+  const size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x;
+  const int sc = sector[blockIdx.y];
+  if (i >= n16 || sc == 0) return;
+  const size_t off = blockIdx.y * vstride + i * 16;
+  const int j = static_cast<int>((i / Nh) % (12 / cpb));
+  Cx<real> v[cpb];
+  Block<P>::load(x + off, v);
+#pragma unroll
+  for (int k = 0; k < cpb; ++k) {
+    const bool upper = j * cpb + k < 6;
+    if (upper != (sc > 0)) v[k] = {real(0), real(0)};
+  }
+  Block<P>::store(x + off, v);
+}
+
 template <int P>
 __global__ void gamma5_kernel(size_t n16, int Nh, const char* x, char* y, size_t vstride) {
   using real = typename Prec<P>::real;
@@ -241,6 +262,13 @@ struct G5L {
   }
 };
 template <int P>
+struct ChiralL {
+  static void run(size_t n16, int Nh, void* x, int nrhs, size_t vs, const int* sector, hipStream_t s) {
+    dim3 grid((n16 + 255) / 256, nrhs);
+    hipLaunchKernelGGL(chiral_kernel<P>, grid, dim3(256), 0, s, n16, Nh, static_cast<char*>(x), vs, sector);
+  }
+};
+template <int P>
 struct DotL {
   static void run(size_t n16, const void* x, const void* y, int nrhs, size_t vs, double* out, hipStream_t s) {
     WsBuf part(static_cast<size_t>(nrhs) * RED_BLOCKS * 2 * sizeof(double), s);
@@ -330,6 +358,13 @@ void blas_axpby(int px, const void* x, const double* a, int py, void* y, const d
 void blas_zero(void* y, size_t bytes, hipStream_t s) {
   const size_t n16 = bytes / 16;
   hipLaunchKernelGGL(zero_kernel, dim3((n16 + 255) / 256), dim3(256), 0, s, n16, static_cast<uint4*>(y));
+  OVL_HIP(hipGetLastError());
+}
+
+void blas_chiral(int prec, size_t vstride, void* x, int nrhs, const int* dev_sector, hipStream_t s) {
+  const size_t n16 = vstride / 16;
+  const int Nh = static_cast<int>(n16 / (2 * spinor_blocks(prec)));
+  dispatch_prec<ChiralL>(prec, n16, Nh, x, nrhs, vstride, dev_sector, s);
   OVL_HIP(hipGetLastError());
 }
 

@@ -53,6 +53,8 @@ void blas_xpay(int prec, size_t n16, const void* x, const double* a, void* y, in
                hipStream_t s);
 // y = gamma5 x for a batch of nrhs vectors of vstride bytes each.
 void blas_gamma5(int prec, size_t vstride, const void* x, void* y, int nrhs, hipStream_t s);
+// In place: keep chirality dev_sector[r] (+1 or -1; 0 = unchanged) of vector r.
+void blas_chiral(int prec, size_t vstride, void* x, int nrhs, const int* dev_sector, hipStream_t s);
 void blas_convert(int sprec, const void* src, int dprec, void* dst, size_t nsites, int nrhs, hipStream_t s);
 // y(py) = a x(px) + b y(py) for a batch of nrhs lattice vectors (nsites
 // sites each); a, b: device arrays of one complex (re, im) per rhs; b may be

@@ -50,6 +50,7 @@ struct Scalars {
   double dot_tmp[2 * OVL_MAX_RHS];
   int active[OVL_MAX_RHS];
   int bad[OVL_MAX_RHS];  // 1 breakdown (p^dag p <= 0), 2 NaN/Inf
+  int sector[OVL_MAX_RHS];  // chiral inner solves: +1 or -1 per rhs
 };
 
 // dot results arrive as (re, im) pairs; keep the real parts.
@@ -118,6 +119,20 @@ struct Solver {
     st->sign_applies += R;
     st->dslash_applies += R * (inner ? per_sign_dw_in : per_sign_dw);
   }
+  // chiral sector operator: out = P_s [c0 in + c1 gamma5 sign(H_w) in] for
+  // in = P_s in, which is D(m) D(m)^dag in when sign^2 = 1
+  void achiral(void* out, const void* in, int prec, Scalars* S) {
+    const double c0 = 2.0 * rho * rho + 0.5 * m * m, c1 = 2.0 * (rho * rho - 0.25 * m * m);
+    overlap_combine(out, in, u, rho, c0, c1, sg_in, lm, prec, R, s);
+    blas_chiral(prec, vP, out, R, S->sector, s);
+    st->sign_applies += R;
+    st->dslash_applies += R * per_sign_dw_in;
+  }
+  // real part of p^dag q per rhs
+  void rdot(const void* x, const void* y, int prec, double* dev_out, Scalars* S) {
+    blas_dot(prec, (prec == OVL_F64 ? v64 : vP) / 16, x, y, R, prec == OVL_F64 ? v64 : vP, S->dot_tmp, s);
+    hipLaunchKernelGGL(take_real_kernel, dim3(1), dim3(64), 0, s, R, S->dot_tmp, dev_out);
+  }
   void norm2(const void* x, int prec, double* dev_out, Scalars* S) {
     blas_norm2(prec, (prec == OVL_F64 ? v64 : vP) / 16, x, R, prec == OVL_F64 ? v64 : vP, S->dot_tmp, s);
     hipLaunchKernelGGL(take_real_kernel, dim3(1), dim3(64), 0, s, R, S->dot_tmp, dev_out);
@@ -140,6 +155,13 @@ int cg_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, doub
   const int P = opt.inner_prec;
   check_prec(P);
   const int check_every = std::max(1, opt.check_every);
+  // chiral inner solves; switched off for the rest of the solve when a
+  // chiral cycle breaks down or fails to halve the true residual (the
+  // sector operator is only positive to within the sign error times
+  // 2 rho^2, which must stay below m^2)
+  bool chiral = opt.chiral != 0;
+  OVL_REQUIRE(!chiral || !(opt.harvest_x && opt.harvest_b && opt.harvest_cap > 0), OVL_E_ARG,
+              "chiral solves do not harvest training pairs");
 
   Solver S{};
   S.u = u;
@@ -171,6 +193,7 @@ int cg_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, doub
 
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
+  bool graph_chiral = false;
   int rc = OVL_OK;
   try {
     WsBuf r64(S.v64 * R, s), tmp64(S.v64 * R, s), e64(S.v64 * R, s);
@@ -224,8 +247,22 @@ int cg_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, doub
       blas_axpby(P, t.p, dS->one, P, p.p, dS->beta, S.nsites, R, s);
     };
 
+    // chiral inner iteration: CG on A = P_s D D^dag P_s for y (e64 holds y)
+    auto body_chiral = [&]() {
+      S.achiral(q.p, p.p, P, dS);
+      S.rdot(p.p, q.p, P, dS->pp, dS);
+      hipLaunchKernelGGL(alpha_kernel, dim3(1), dim3(64), 0, s, R, dS);
+      blas_axpby(P, p.p, dS->alpha, OVL_F64, e64.p, dS->one, S.nsites, R, s);
+      blas_axpby(P, q.p, dS->malpha, P, rin.p, dS->one, S.nsites, R, s);
+      S.norm2(rin.p, P, dS->rrn, dS);
+      hipLaunchKernelGGL(beta_kernel, dim3(1), dim3(64), 0, s, R, dS);
+      blas_axpby(P, rin.p, dS->one, P, p.p, dS->beta, S.nsites, R, s);
+    };
+
     const double rms_target = P == OVL_F64 ? 1.0 : std::sqrt(12.0 * S.nsites) / 8.0;
     int its = 0;
+    bool chiral_failed = false;
+    double prev_worst_chiral = 0.0;
     st->restarts = 0;
     for (;;) {
       // true residual r = b - D(m) x in FP64
@@ -247,11 +284,26 @@ int cg_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, doub
       if (log_on())
         fprintf(stderr, "[ovl cg] cycle %d: %d iterations, max FP64 true residual %.3e\n", st->restarts, its, worst);
       if (done) break;
+      if (chiral && prev_worst_chiral > 0.0 && worst > 0.5 * prev_worst_chiral) {
+        if (log_on()) fprintf(stderr, "[ovl cg] chiral cycle did not halve the residual: switching to D D^dag\n");
+        chiral = false;
+      }
       if (its >= maxiter || st->restarts >= opt.max_restarts) {
         rc = OVL_W_NOT_CONVERGED;
         break;
       }
       ++st->restarts;
+
+      // chiral: per rhs the sector with the larger part of r,
+      // ||P_+- r||^2 = (||r||^2 +- Re r^dag gamma5 r) / 2
+      if (chiral) {
+        blas_gamma5(OVL_F64, S.v64, r64.p, tmp64.p, R, s);
+        S.rdot(r64.p, tmp64.p, OVL_F64, dS->pp, dS);
+        std::vector<double> g5r(R);
+        OVL_HIP(hipMemcpyAsync(g5r.data(), dS->pp, sizeof(double) * R, hipMemcpyDeviceToHost, s));
+        OVL_HIP(hipStreamSynchronize(s));
+        for (int r = 0; r < R; ++r) hS.sector[r] = g5r[r] >= 0.0 ? 1 : -1;
+      }
 
       // inner system D e = r / scale, scale chosen so the rms element of the
       // scaled residual is O(1/8) (keeps FP16 iterates away from under/overflow)
@@ -276,18 +328,31 @@ int cg_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, doub
       OVL_HIP(hipStreamSynchronize(s));
       blas_axpby(OVL_F64, r64.p, dS->iscale, P, rin.p, nullptr, S.nsites, R, s);
       blas_zero(e64.p, S.v64 * R, s);
-      S.norm2(rin.p, P, dS->rr, dS);
-      S.dm(p.p, rin.p, P, 1, true);
+      if (chiral) {
+        blas_chiral(P, S.vP, rin.p, R, dS->sector, s);
+        S.norm2(rin.p, P, dS->rr, dS);
+        blas_axpby(P, rin.p, dS->one, P, p.p, nullptr, S.nsites, R, s);
+      } else {
+        S.norm2(rin.p, P, dS->rr, dS);
+        S.dm(p.p, rin.p, P, 1, true);
+      }
 
       int inner = 0;
       for (;;) {
         int step;
         if (opt.graph_chunk > 0 && inner > 0 && !harvest) {
+          if (gexec && graph_chiral != chiral) {
+            OVL_HIP(hipGraphExecDestroy(gexec));
+            OVL_HIP(hipGraphDestroy(graph));
+            gexec = nullptr;
+            graph = nullptr;
+          }
           if (!gexec) {
             capturing = true;
             OVL_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
             const int64_t sa = st->sign_applies, da = st->dslash_applies;
-            for (int k = 0; k < opt.graph_chunk; ++k) body();
+            for (int k = 0; k < opt.graph_chunk; ++k) chiral ? body_chiral() : body();
+            graph_chiral = chiral;
             st->sign_applies = sa;  // captured, not executed: counted at replay
             st->dslash_applies = da;
             OVL_HIP(hipStreamEndCapture(s, &graph));
@@ -296,11 +361,12 @@ int cg_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, doub
           }
           OVL_HIP(hipGraphLaunch(gexec, s));
           step = opt.graph_chunk;
-          st->sign_applies += static_cast<int64_t>(2) * R * step;
-          st->dslash_applies += static_cast<int64_t>(2) * R * step * S.per_sign_dw_in;
+          const int sa_per_it = chiral ? 1 : 2;
+          st->sign_applies += static_cast<int64_t>(sa_per_it) * R * step;
+          st->dslash_applies += static_cast<int64_t>(sa_per_it) * R * step * S.per_sign_dw_in;
         } else {
           const int nrun = (opt.graph_chunk > 0 || harvest) ? 1 : check_every;
-          for (int k = 0; k < nrun; ++k) body();
+          for (int k = 0; k < nrun; ++k) chiral ? body_chiral() : body();
           step = nrun;
         }
         if (log_on() && (its + step) / 100 != its / 100)
@@ -309,16 +375,35 @@ int cg_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, doub
         its += step;
         OVL_HIP(hipMemcpyAsync(hS.active, dS->active, sizeof(hS.active) + sizeof(hS.bad), hipMemcpyDeviceToHost, s));
         OVL_HIP(hipStreamSynchronize(s));
-        bool any = false;
+        bool any = false, broke = false;
         for (int r = 0; r < R; ++r) {
-          if (hS.bad[r] == 2) throw Error(OVL_E_NAN, "NaN or Inf in a CG iterate");
-          if (hS.bad[r] == 1) throw Error(OVL_E_BREAKDOWN, "CG breakdown: p^dag p <= 0");
+          if (hS.bad[r] == 2 && !chiral) throw Error(OVL_E_NAN, "NaN or Inf in a CG iterate");
+          if (hS.bad[r] == 1 && !chiral) throw Error(OVL_E_BREAKDOWN, "CG breakdown: p^dag p <= 0");
+          broke = broke || hS.bad[r] != 0;
           any = any || hS.active[r];
+        }
+        if (broke) {
+          chiral_failed = true;
+          break;
         }
         if (!any || its >= maxiter) break;
       }
-      // x += scale * e
-      blas_axpby(OVL_F64, e64.p, dS->scale, OVL_F64, x, dS->one, S.nsites, R, s);
+      if (chiral_failed) {
+        // discard this cycle's correction and continue with D D^dag
+        if (log_on()) fprintf(stderr, "[ovl cg] chiral sector operator not positive: switching to D D^dag\n");
+        chiral = false;
+        chiral_failed = false;
+        continue;
+      }
+      if (chiral) {
+        prev_worst_chiral = worst;
+        // e = D(m)^dag y in FP64 (inner sign), into tmp64
+        S.dm(tmp64.p, e64.p, OVL_F64, 1, true);
+        blas_axpby(OVL_F64, tmp64.p, dS->scale, OVL_F64, x, dS->one, S.nsites, R, s);
+      } else {
+        // x += scale * e
+        blas_axpby(OVL_F64, e64.p, dS->scale, OVL_F64, x, dS->one, S.nsites, R, s);
+      }
     }
     st->iterations = its;
     OVL_HIP(hipStreamSynchronize(s));

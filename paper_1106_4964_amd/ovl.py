@@ -80,6 +80,7 @@ class SolveOpts(ctypes.Structure):
         ("harvest_b", ctypes.c_void_p),
         ("harvest_cap", ctypes.c_int),
         ("inner_sign", ctypes.c_void_p),
+        ("chiral", ctypes.c_int),
     ]
 
 

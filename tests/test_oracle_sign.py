@@ -169,6 +169,26 @@ def test_massive_overlap_normal_identity(small):
     assert abs(a - b) < 1e-12 * abs(a)
 
 
+@pytest.mark.parametrize("chir", [1, -1])
+def test_chiral_sector_operator(small, chir):
+    """On a vector of chirality s (gamma5 v = s v), with the exact sign,
+    D(m) D(m)^dag v = (2 rho^2 + m^2/2) v + 2 s (rho^2 - m^2/4) P_s sign(H_w) v
+    with P_s = (1 + s gamma5)/2 (eq. 3 and 8), and D D^dag keeps the sector."""
+    lat, U, H, lo, hi = small
+    rho, m = 1.5, 0.03
+    n = H.shape[0]
+    G5 = dense.dense_gamma5(lat)
+    E = dense.exact_sign(H)
+    Dm = (rho + m / 2) * np.eye(n) + (rho - m / 2) * G5 @ E
+    Ps = 0.5 * (np.eye(n) + chir * G5)
+    v = Ps @ si.gaussian_spinor(lat.dims, 107).reshape(-1)
+    assert np.linalg.norm(G5 @ v - chir * v) < 1e-14 * np.linalg.norm(v)
+    lhs = Dm @ (Dm.conj().T @ v)
+    rhs = (2 * rho * rho + m * m / 2) * v + 2 * chir * (rho * rho - m * m / 4) * (Ps @ (E @ v))
+    assert np.linalg.norm(lhs - rhs) < 1e-12 * np.linalg.norm(lhs)
+    assert np.linalg.norm(lhs - Ps @ lhs) < 1e-12 * np.linalg.norm(lhs)
+
+
 def test_free_field_overlap_closed_form():
     """U = 1: D(p) = 1 + (M(p) + i gamma.sin p)/omega(p), M = -rho + sum(1-cos p)."""
     lat = Lattice((4, 4, 2, 2))
