@@ -367,12 +367,14 @@ int ovl_net_train(ovl_net* n, const ovl_gauge* u, const void* B, const void* X, 
 int ovl_net_apply(const ovl_net* n, const ovl_gauge* u, const void* in, void* out, ovl_stream_t s);
 
 /* ovl_stencil_tune: mode 1 (default; OVL_TUNE=0 in the environment starts
- *   with 0) times every candidate shape of a stencil configuration once,
- *   with HIP events on a scratch output, and keeps the fastest: KR
- *   right-hand sides per thread (each link loaded once per KR vectors; KR
- *   divides nrhs, KR <= 4, <= 2 for FP64) and 128 or 256 threads per block.
- *   Mode 0 uses the largest allowed KR and 256 threads.  Changing the mode
- *   clears the tuned table.  Launches inside a HIP graph capture never tune.
+ *   with 0) tunes each stencil configuration (precision, link format, extra
+ *   epilogue vectors, batch size, parity mode, volume) at its first launch:
+ *   every candidate shape is timed with HIP events on a scratch output in
+ *   two rounds of one warm-up and three timed launches, and the first
+ *   candidate within 2% of the fastest is kept.  Mode 0 uses the largest
+ *   allowed KR (KR divides nrhs, KR <= 4, <= 2 for FP64) and 256 threads.
+ *   Changing the mode clears the tuned table.  Launches inside a HIP graph
+ *   capture never tune (they use the default until a tuned shape exists).
  *   Candidate shapes: (a) KR vectors per thread, one lattice pass per
  *   group of KR vectors, 128 or 256 threads; (b) the same with all
  *   nrhs/KR groups side by side in one workgroup (32 or 64 sites x groups
