@@ -51,46 +51,58 @@ __device__ inline double wsum(double v) {
   return v;
 }
 
-// partial[(i*G + b)*R + r] = sum over block b's tiles of conj(V_i) psi_r.
-// blockIdx.y selects a group of PJ_WAVES*IW basis vectors; each wave owns IW.
-template <int PP, int RMAX, int IW>
+// partial[(i*G + b)*R + r] = sum over K-block b's tiles of conj(V_i) psi_r.
+// blockIdx.x selects a group of PJ_WAVES*IW basis vectors (each wave owns
+// IW), blockIdx.y the K-block; the groups of one K-block are neighbours in
+// launch order, so they share the batch tiles in cache.  Each tile of the
+// batch is staged in LDS (as FP64) once per block.
+// EX: the batch has exactly RMAX vectors (R is a compile-time constant, so
+// per-rhs guards and coefficient strides fold away).
+template <int PP, int RMAX, int IW, bool EX>
 __global__ __launch_bounds__(PJ_WAVES * 64) void dot_kernel(int Nh, int ell, const char* V, size_t vstrideV,
                                                              const char* psi, size_t vstrideP, int R,
                                                              double2* partial) {
+  if constexpr (EX) R = RMAX;
   __shared__ Cx<double> tile[RMAX][PJ_TILE];
   const int tiles_per_row = (Nh + PJ_TILE - 1) / PJ_TILE;
   const long total = 24L * tiles_per_row;
-  const long t0 = total * blockIdx.x / gridDim.x, t1 = total * (blockIdx.x + 1) / gridDim.x;
+  const int G = gridDim.y, kb = blockIdx.y;
+  const long t0 = total * kb / G, t1 = total * (kb + 1) / G;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int ibase = (blockIdx.y * PJ_WAVES + wave) * IW;
+  const int ibase = (blockIdx.x * PJ_WAVES + wave) * IW;
   Cx<double> acc[IW][RMAX];
 #pragma unroll
   for (int j = 0; j < IW; ++j)
 #pragma unroll
     for (int r = 0; r < RMAX; ++r) acc[j][r] = {0.0, 0.0};
 
+  // t runs over (tile, row) with the row fastest, so the 24 rows of a site
+  // tile, which share the batch's 16-byte blocks, are read back to back
   for (long t = t0; t < t1; ++t) {
-    const int row = static_cast<int>(t / tiles_per_row);
-    const int h0 = static_cast<int>(t % tiles_per_row) * PJ_TILE;
+    const int row = static_cast<int>(t % 24);
+    const int h0 = static_cast<int>(t / 24) * PJ_TILE;
+    const int h = h0 + lane;
+    // this tile's basis elements are loaded before the barrier
+    Cx<double> v[IW];
+#pragma unroll
+    for (int j = 0; j < IW; ++j)
+      v[j] = (ibase + j < ell && h < Nh) ? load_cx<OVL_F64>(V + (ibase + j) * vstrideV, row, h, Nh)
+                                         : Cx<double>{0.0, 0.0};
     __syncthreads();
     for (int k = threadIdx.x; k < R * PJ_TILE; k += blockDim.x) {
       const int r = k / PJ_TILE, l = k % PJ_TILE;
       tile[r][l] = (h0 + l < Nh) ? load_cx<PP>(psi + r * vstrideP, row, h0 + l, Nh) : Cx<double>{0.0, 0.0};
     }
     __syncthreads();
-    const int h = h0 + lane;
-    if (h < Nh) {
-      Cx<double> ps[RMAX];
 #pragma unroll
-      for (int r = 0; r < RMAX; ++r) ps[r] = (r < R) ? tile[r][lane] : Cx<double>{0.0, 0.0};
+    for (int r = 0; r < RMAX; ++r) {
+      const Cx<double> ps = (r < R) ? tile[r][lane] : Cx<double>{0.0, 0.0};
 #pragma unroll
-      for (int j = 0; j < IW; ++j) {
-        const int i = ibase + j;
-        if (i < ell) {
-          const Cx<double> v = load_cx<OVL_F64>(V + i * vstrideV, row, h, Nh);
-#pragma unroll
-          for (int r = 0; r < RMAX; ++r) acc[j][r] = acc[j][r] + cmul_conj(v, ps[r]);
-        }
+      for (int j = 0; j < IW; ++j) {  // acc += conj(v) ps, four FMAs
+        acc[j][r].re = fma(v[j].re, ps.re, acc[j][r].re);
+        acc[j][r].re = fma(v[j].im, ps.im, acc[j][r].re);
+        acc[j][r].im = fma(v[j].re, ps.im, acc[j][r].im);
+        acc[j][r].im = fma(-v[j].im, ps.re, acc[j][r].im);
       }
     }
   }
@@ -101,7 +113,7 @@ __global__ __launch_bounds__(PJ_WAVES * 64) void dot_kernel(int Nh, int ell, con
     for (int r = 0; r < RMAX; ++r) {
       const double re = wsum(acc[j][r].re), im = wsum(acc[j][r].im);
       if (lane == 0 && i < ell && r < R)
-        partial[(static_cast<size_t>(i) * gridDim.x + blockIdx.x) * R + r] = make_double2(re, im);
+        partial[(static_cast<size_t>(i) * G + kb) * R + r] = make_double2(re, im);
     }
   }
 }
@@ -121,14 +133,14 @@ __global__ void dot_reduce_kernel(int ell, int R, int G, const double2* partial,
 }
 
 // Y_r = [Y_r] + sum_i V_i K[i*R + r]; one thread per element, K in LDS.
-template <int PP, int RMAX, bool KEEP>
+template <int PP, int RMAX, bool KEEP, bool EX>
 __global__ __launch_bounds__(256) void axpy_kernel(int Nh, int ell, const char* V, size_t vstrideV,
-                                                   const double2* K, char* Y, size_t vstrideP, int R) {
-  extern __shared__ double2 coef[];
-  for (int k = threadIdx.x; k < ell * R; k += blockDim.x) coef[k] = K[k];
-  __syncthreads();
-  const int row = blockIdx.y;
-  const int h = blockIdx.x * blockDim.x + threadIdx.x;
+                                                   const double2* __restrict__ coef, char* Y, size_t vstrideP,
+                                                   int R) {
+  if constexpr (EX) R = RMAX;
+  // coef[i*R + r] is the same for the whole wave: scalar loads
+  const int row = blockIdx.x % 24;  // rows of a site tile in consecutive blocks
+  const int h = (blockIdx.x / 24) * blockDim.x + threadIdx.x;
   if (h >= Nh) return;
   Cx<double> y[RMAX];
 #pragma unroll
@@ -140,7 +152,10 @@ __global__ __launch_bounds__(256) void axpy_kernel(int Nh, int ell, const char* 
     for (int r = 0; r < RMAX; ++r) {
       if (r < R) {
         const double2 cc = coef[i * R + r];
-        y[r] = y[r] + v * Cx<double>{cc.x, cc.y};
+        y[r].re = fma(v.re, cc.x, y[r].re);
+        y[r].re = fma(-v.im, cc.y, y[r].re);
+        y[r].im = fma(v.re, cc.y, y[r].im);
+        y[r].im = fma(v.im, cc.x, y[r].im);
       }
     }
   }
@@ -150,15 +165,15 @@ __global__ __launch_bounds__(256) void axpy_kernel(int Nh, int ell, const char* 
 }
 
 // psi_h = psi - sum_i C_i eta_i, w = [gamma5] sum_i sign_i C_i eta_i.
-template <int PP, int RMAX>
+template <int PP, int RMAX, bool EX>
 __global__ __launch_bounds__(256) void project_kernel(int Nh, int ell, const char* V, size_t vstrideV,
                                                       const char* psi, char* psih, char* w, size_t vstrideP, int R,
-                                                      const double2* C, const double* sgn, int g5w) {
-  extern __shared__ double2 coef[];
-  for (int k = threadIdx.x; k < ell * R; k += blockDim.x) coef[k] = C[k];
-  __syncthreads();
-  const int row = blockIdx.y;
-  const int h = blockIdx.x * blockDim.x + threadIdx.x;
+                                                      const double2* __restrict__ coef,
+                                                      const double* __restrict__ sgn, int g5w) {
+  if constexpr (EX) R = RMAX;
+  // coef[i*R + r] and sgn[i] are the same for the whole wave: scalar loads
+  const int row = blockIdx.x % 24;  // rows of a site tile in consecutive blocks
+  const int h = (blockIdx.x / 24) * blockDim.x + threadIdx.x;
   if (h >= Nh) return;
   Cx<double> ph[RMAX], ww[RMAX];
 #pragma unroll
@@ -173,9 +188,11 @@ __global__ __launch_bounds__(256) void project_kernel(int Nh, int ell, const cha
     for (int r = 0; r < RMAX; ++r) {
       if (r < R) {
         const double2 cc = coef[i * R + r];
-        const Cx<double> vc = v * Cx<double>{cc.x, cc.y};
-        ph[r] = ph[r] - vc;
-        ww[r] = ww[r] + s * vc;
+        const double vr = v.re * cc.x - v.im * cc.y, vi = v.re * cc.y + v.im * cc.x;
+        ph[r].re -= vr;
+        ph[r].im -= vi;
+        ww[r].re = fma(s, vr, ww[r].re);
+        ww[r].im = fma(s, vi, ww[r].im);
       }
     }
   }
@@ -215,13 +232,13 @@ __global__ __launch_bounds__(256) void rotate_kernel(int Nh, int K, int k, char*
   }
 }
 
-template <int PP, int RMAX, int IW>
+template <int PP, int RMAX, int IW, bool EX = false>
 void dot_go(const ovl_geom* g, const void* V, int ell, const void* psi, int R, double2* C, hipStream_t s) {
   const int Nh = g->geo.Nh;
   const size_t vsV = spinor_vec_bytes(g, OVL_F64), vsP = spinor_vec_bytes(g, PP);
   const int groups = (ell + PJ_WAVES * IW - 1) / (PJ_WAVES * IW);
   WsBuf part(static_cast<size_t>(ell) * PJ_BLOCKS * R * sizeof(double2), s);
-  hipLaunchKernelGGL((dot_kernel<PP, RMAX, IW>), dim3(PJ_BLOCKS, groups), dim3(PJ_WAVES * 64), 0, s, Nh, ell,
+  hipLaunchKernelGGL((dot_kernel<PP, RMAX, IW, EX>), dim3(groups, PJ_BLOCKS), dim3(PJ_WAVES * 64), 0, s, Nh, ell,
                      static_cast<const char*>(V), vsV, static_cast<const char*>(psi), vsP, R,
                      static_cast<double2*>(part.p));
   OVL_HIP(hipGetLastError());
@@ -232,47 +249,41 @@ void dot_go(const ovl_geom* g, const void* V, int ell, const void* psi, int R, d
 
 template <int PP>
 void dot_r(const ovl_geom* g, const void* V, int ell, const void* psi, int R, double2* C, hipStream_t s) {
-  if (R == 1) dot_go<PP, 1, 8>(g, V, ell, psi, R, C, s);
+  if (R == 1) dot_go<PP, 1, 8, true>(g, V, ell, psi, R, C, s);
   else if (R <= 4) dot_go<PP, 4, 4>(g, V, ell, psi, R, C, s);
+  else if (R == 12) dot_go<PP, 12, 2, true>(g, V, ell, psi, R, C, s);
   else dot_go<PP, 12, 2>(g, V, ell, psi, R, C, s);
 }
 
-size_t coef_lds(int ell, int R) {
-  const size_t lds = static_cast<size_t>(ell) * R * sizeof(double2);
-  OVL_REQUIRE(lds <= 64 * 1024, OVL_E_ARG, "block operation: basis size * nrhs too large (max 4096)");
-  return lds;
-}
-
-template <int PP, int RMAX>
+template <int PP, int RMAX, bool EX = false>
 void axpy_go(const ovl_geom* g, const void* V, int ell, const double2* K, void* Y, int R, bool keep, hipStream_t s) {
   const int Nh = g->geo.Nh;
   const size_t vsV = spinor_vec_bytes(g, OVL_F64), vsP = spinor_vec_bytes(g, PP);
-  const size_t lds = coef_lds(ell, R);
-  dim3 grid((Nh + 255) / 256, 24);
+  dim3 grid(((Nh + 255) / 256) * 24);
   if (keep)
-    hipLaunchKernelGGL((axpy_kernel<PP, RMAX, true>), grid, dim3(256), lds, s, Nh, ell, static_cast<const char*>(V),
+    hipLaunchKernelGGL((axpy_kernel<PP, RMAX, true, EX>), grid, dim3(256), 0, s, Nh, ell, static_cast<const char*>(V),
                        vsV, K, static_cast<char*>(Y), vsP, R);
   else
-    hipLaunchKernelGGL((axpy_kernel<PP, RMAX, false>), grid, dim3(256), lds, s, Nh, ell,
+    hipLaunchKernelGGL((axpy_kernel<PP, RMAX, false, EX>), grid, dim3(256), 0, s, Nh, ell,
                        static_cast<const char*>(V), vsV, K, static_cast<char*>(Y), vsP, R);
   OVL_HIP(hipGetLastError());
 }
 
 template <int PP>
 void axpy_r(const ovl_geom* g, const void* V, int ell, const double2* K, void* Y, int R, bool keep, hipStream_t s) {
-  if (R == 1) axpy_go<PP, 1>(g, V, ell, K, Y, R, keep, s);
+  if (R == 1) axpy_go<PP, 1, true>(g, V, ell, K, Y, R, keep, s);
   else if (R <= 4) axpy_go<PP, 4>(g, V, ell, K, Y, R, keep, s);
+  else if (R == 12) axpy_go<PP, 12, true>(g, V, ell, K, Y, R, keep, s);
   else axpy_go<PP, 12>(g, V, ell, K, Y, R, keep, s);
 }
 
-template <int PP, int RMAX>
+template <int PP, int RMAX, bool EX = false>
 void project_go(const ovl_lowmodes* lm, const void* psi, void* psih, void* w, int R, int g5w, const double2* C,
                 hipStream_t s) {
   const ovl_geom* g = &lm->geom;
   const int Nh = g->geo.Nh;
   const size_t vsV = spinor_vec_bytes(g, OVL_F64), vsP = spinor_vec_bytes(g, PP);
-  const size_t lds = coef_lds(lm->ell, R);
-  hipLaunchKernelGGL((project_kernel<PP, RMAX>), dim3((Nh + 255) / 256, 24), dim3(256), lds, s, Nh, lm->ell,
+  hipLaunchKernelGGL((project_kernel<PP, RMAX, EX>), dim3(((Nh + 255) / 256) * 24), dim3(256), 0, s, Nh, lm->ell,
                      static_cast<const char*>(lm->V), vsV, static_cast<const char*>(psi), static_cast<char*>(psih),
                      static_cast<char*>(w), vsP, R, C, lm->dev_sign, g5w);
   OVL_HIP(hipGetLastError());
@@ -281,8 +292,9 @@ void project_go(const ovl_lowmodes* lm, const void* psi, void* psih, void* w, in
 template <int PP>
 void project_r(const ovl_lowmodes* lm, const void* psi, void* psih, void* w, int R, int g5w, const double2* C,
                hipStream_t s) {
-  if (R == 1) project_go<PP, 1>(lm, psi, psih, w, R, g5w, C, s);
+  if (R == 1) project_go<PP, 1, true>(lm, psi, psih, w, R, g5w, C, s);
   else if (R <= 4) project_go<PP, 4>(lm, psi, psih, w, R, g5w, C, s);
+  else if (R == 12) project_go<PP, 12, true>(lm, psi, psih, w, R, g5w, C, s);
   else project_go<PP, 12>(lm, psi, psih, w, R, g5w, C, s);
 }
 
