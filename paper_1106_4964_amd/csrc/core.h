@@ -217,6 +217,8 @@ struct Block<OVL_BF16> {
   }
 };
 
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+
 // One spinor (12 complex) of a field in the [parity][block][Nh] layout.
 // `base` points at the start of the vector, `h` is the half-lattice index,
 // `p` the parity.
@@ -234,6 +236,26 @@ struct SpinorIO {
     char* b = static_cast<char*>(base) + (static_cast<size_t>(p) * nb * Nh + h) * 16;
 #pragma unroll
     for (int j = 0; j < nb; ++j) Block<P>::store(b + static_cast<size_t>(j) * Nh * 16, s + j * cpb);
+  }
+  // Streaming variants for data touched once per launch (epilogue vectors,
+  // the output): non-temporal, so they do not displace the neighbour and
+  // link lines the stencil reuses from L2.
+  __device__ static inline void load_nt(const void* base, int p, int h, int Nh, Cx<real>* s) {
+    const char* b = static_cast<const char*>(base) + (static_cast<size_t>(p) * nb * Nh + h) * 16;
+#pragma unroll
+    for (int j = 0; j < nb; ++j) {
+      const u32x4_t v = __builtin_nontemporal_load(reinterpret_cast<const u32x4_t*>(b + static_cast<size_t>(j) * Nh * 16));
+      Block<P>::load(&v, s + j * cpb);
+    }
+  }
+  __device__ static inline void store_nt(void* base, int p, int h, int Nh, const Cx<real>* s) {
+    char* b = static_cast<char*>(base) + (static_cast<size_t>(p) * nb * Nh + h) * 16;
+#pragma unroll
+    for (int j = 0; j < nb; ++j) {
+      u32x4_t v;
+      Block<P>::store(&v, s + j * cpb);
+      __builtin_nontemporal_store(v, reinterpret_cast<u32x4_t*>(b + static_cast<size_t>(j) * Nh * 16));
+    }
   }
 };
 

@@ -184,13 +184,13 @@ __device__ inline void epilogue(const StencilArgs& A, size_t off, int p, int h, 
   }
 #pragma unroll
   for (int j = 0; j < NV; ++j) {
-    SpinorIO<P>::load(static_cast<const char*>(A.v[j]) + off, p, h, A.g.Nh, s);
+    SpinorIO<P>::load_nt(static_cast<const char*>(A.v[j]) + off, p, h, A.g.Nh, s);
     const real cj = static_cast<real>(A.cv[j]);
     const real sj = ((A.g5v >> j) & 1) ? -cj : cj;
 #pragma unroll
     for (int c = 0; c < 12; ++c) acc[c] = acc[c] + ((c >= 6) ? sj : cj) * s[c];
   }
-  SpinorIO<P>::store(static_cast<char*>(A.out) + off, p, h, A.g.Nh, acc);
+  SpinorIO<P>::store_nt(static_cast<char*>(A.out) + off, p, h, A.g.Nh, acc);
 }
 
 // Output site (parity p, half index h) of this thread; false past the end.
