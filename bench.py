@@ -42,6 +42,8 @@ HBM_PEAK_GBS = 8000.0
 # stencil configuration: (extra epilogue vectors, tuned shape kr, bs, pipe,
 # rin, tm).  Summary and commands: profiles/stencil_f16_12rhs_24x24x24x64_counters.md
 PROFILED_TRAFFIC = {
+    (3, (2, 128, 0, 0, 0)): 4041877504,
+    (0, (2, 128, 0, 0, 0)): 2987828224,
 }
 
 

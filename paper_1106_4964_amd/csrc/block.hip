@@ -35,6 +35,14 @@ __device__ inline Cx<double> load_cx(const char* base, int row, int h, int Nh) {
   return {static_cast<double>(v.re), static_cast<double>(v.im)};
 }
 
+// Basis elements are read once per sweep: non-temporal, so the batch's
+// blocks (reused across the 24 rows of a site tile) stay in L2.
+__device__ inline Cx<double> load_basis(const char* base, int row, int h, int Nh) {
+  typedef double f64x2_t __attribute__((ext_vector_type(2)));
+  const f64x2_t v = __builtin_nontemporal_load(reinterpret_cast<const f64x2_t*>(base + cx_offset<OVL_F64>(row, h, Nh)));
+  return {v.x, v.y};
+}
+
 template <int P>
 __device__ inline void store_cx(char* base, int row, int h, int Nh, Cx<double> v) {
   using real = typename Prec<P>::real;
@@ -86,7 +94,7 @@ __global__ __launch_bounds__(PJ_WAVES * 64) void dot_kernel(int Nh, int ell, con
     Cx<double> v[IW];
 #pragma unroll
     for (int j = 0; j < IW; ++j)
-      v[j] = (ibase + j < ell && h < Nh) ? load_cx<OVL_F64>(V + (ibase + j) * vstrideV, row, h, Nh)
+      v[j] = (ibase + j < ell && h < Nh) ? load_basis(V + (ibase + j) * vstrideV, row, h, Nh)
                                          : Cx<double>{0.0, 0.0};
     __syncthreads();
     for (int k = threadIdx.x; k < R * PJ_TILE; k += blockDim.x) {
@@ -147,7 +155,7 @@ __global__ __launch_bounds__(256) void axpy_kernel(int Nh, int ell, const char* 
   for (int r = 0; r < RMAX; ++r)
     y[r] = (KEEP && r < R) ? load_cx<PP>(Y + r * vstrideP, row, h, Nh) : Cx<double>{0.0, 0.0};
   for (int i = 0; i < ell; ++i) {
-    const Cx<double> v = load_cx<OVL_F64>(V + i * vstrideV, row, h, Nh);
+    const Cx<double> v = load_basis(V + i * vstrideV, row, h, Nh);
 #pragma unroll
     for (int r = 0; r < RMAX; ++r) {
       if (r < R) {
@@ -182,7 +190,7 @@ __global__ __launch_bounds__(256) void project_kernel(int Nh, int ell, const cha
     ww[r] = {0.0, 0.0};
   }
   for (int i = 0; i < ell; ++i) {
-    const Cx<double> v = load_cx<OVL_F64>(V + i * vstrideV, row, h, Nh);
+    const Cx<double> v = load_basis(V + i * vstrideV, row, h, Nh);
     const double s = sgn[i];
 #pragma unroll
     for (int r = 0; r < RMAX; ++r) {
