@@ -201,12 +201,12 @@ def spectral_setup(ovl, g, gauge, dims, rho, ell, delta, seed_base, tol=1e-12):
     del v0
     m = ell + max(12, ell // 4)
     log("eigensolver: %d of %d vectors" % (ell, m))
+    # Gaussian start block drawn on the device (seeded): any full-rank start
+    # serves the eigensolver, and host generation would take ~0.2 s a vector
     V = torch.empty(g.spinor_bytes(ovl.OVL_F64, m), dtype=torch.uint8, device=dev)
-    for i in range(0, m, 8):
-        k = min(8, m - i)
-        blk = np.stack([si.gaussian_spinor(dims, seed_base + i + j) for j in range(k)])
-        ovl.ovl_pack_spinor(g, torch.from_numpy(blk).to(dev),
-                            V[i * g.spinor_bytes(ovl.OVL_F64):], ovl.OVL_F64, k, None)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed_base)
+    V.view(torch.float64).normal_(generator=gen)
     lams = np.zeros(ell)
     est = ovl.EigStats()
     rc = ovl.ovl_hw_eigs(gauge, rho, ell, m, V, lams, lam_max, tol, 60, 40, ctypes.byref(est), None)

@@ -119,3 +119,41 @@ def test_overlap_16x16x16x32_each_precision():
         err = gu.rel_err(gu.unpack(g, y, prec), want)
         print("D(m) 16^3x32 prec %d: rel err %.2e" % (prec, err))
         assert err < bound
+
+
+def test_mixed_cg_16x16x16x32_one_rhs():
+    """The 16^3x32 single-rhs case: 20 low modes from the GPU eigensolver,
+    mixed CG (F16 inner, FP64 defect correction) at m = 0.01 to 1e-10, the
+    solution judged by the oracle's own operator on the same coefficients
+    and low modes."""
+    dims = (16, 16, 16, 32)
+    lat = Lattice(dims)
+    U = si.gauge_field(dims, 0.25, 13)
+    g = ovl.Geometry(dims)
+    gauge = gu.make_gauge(g, U, [(F16, 1)])
+    v0 = gu.pack(g, si.gaussian_spinor(dims, 17), F64)
+    lam = ctypes.c_double()
+    ovl.ovl_hw_bound(gauge, RHO, v0, 60, ctypes.byref(lam), None, None, None)
+    lam_max = lam.value * (1 + 1e-6)
+    ell, m_ = 20, 32
+    V = gu.pack(g, np.stack([si.gaussian_spinor(dims, 2000 + i) for i in range(m_)]), F64, m_)
+    lams = np.zeros(ell)
+    est = ovl.EigStats()
+    assert ovl.ovl_hw_eigs(gauge, RHO, ell, m_, V, lams, lam_max, 1e-11, 60, 30, ctypes.byref(est), None) == 0
+    Vk = V[: ell * g.spinor_bytes(F64)]
+    lm = ovl.LowModes(g, Vk, lams)
+    s = ovl.Sign(abs(lams[-1]), lam_max, delta=1e-6)
+    b = si.point_source(dims, 0, 0)[None]
+    x = gu.pack(g, np.zeros_like(b), F64, 1)
+    st = ovl.SolveStats()
+    rc = ovl.ovl_cg_solve(x, gu.pack(g, b, F64, 1), 1, gauge, RHO, 0.01, s, lm, 1e-10, 20000,
+                          ovl.SolveOpts(F16, 1e-2, 4, 1, 60), ctypes.byref(st), None)
+    assert rc == 0 and st.true_residual[0] <= 1e-10
+    so = sign.SignApprox(lam_max=lam_max, eps=s.eps, coeffs=s.coeffs())
+    Vh = gu.unpack(g, Vk, F64, ell)
+    xs = gu.unpack(g, x, F64)
+    res = b[0] - sign.overlap_apply(lat, U, xs, RHO, 0.01, so, Vh, lams)
+    rel = np.linalg.norm(res) / np.linalg.norm(b[0])
+    print("16^3x32 mixed CG: n = %d, %d iterations, %d restarts, oracle residual %.2e"
+          % (s.n, st.iterations, st.restarts, rel))
+    assert rel <= 1.05e-10
