@@ -293,6 +293,22 @@ int ovl_cg_solve(void* x, const void* b, int nrhs, const ovl_gauge* u, double rh
 int ovl_fgcr_solve(void* x, const void* b, int nrhs, const ovl_gauge* u, double rho, double m, const ovl_sign* sign,
                    const ovl_lowmodes* lowmodes, const ovl_net* M, int restart, double tol, int maxiter,
                    const ovl_solve_opts* opts, ovl_solve_stats* stats, ovl_stream_t s);
+/* ovl_cg_multimass: solves D(m_j) x_j = b for nmass <= 8 masses at once
+ *   (eq. 3 and 8): with sign^2 = 1, D(m) D(m)^dag = c(m) (K + sigma(m)) with
+ *   K = gamma5 sign + sign gamma5, c = rho^2 - m^2/4 and
+ *   sigma = (2 rho^2 + m^2/2) / c, so all masses share one Krylov space.  A
+ *   shifted CG on K + sigma (two sign applications per iteration, at
+ *   opts->inner_prec and to opts->inner_tol, FP64 vectors) gives every y_j;
+ *   x_j = D(m_j)^dag y_j / c_j; then each x_j is finished by the FP64
+ *   defect-correction loop of ovl_cg_solve (same opts).  x: nmass separate
+ *   caller buffers of nrhs FP64 vectors (overwritten); stats: nmass entries,
+ *   entry j for mass j's correction solve, the shared shifted stage added to
+ *   the entry of the lightest mass.  Errors as ovl_cg_solve; OVL_E_ARG for
+ *   chiral mode or harvesting.
+ */
+int ovl_cg_multimass(void* const* x, const void* b, int nrhs, const ovl_gauge* u, double rho, const double* masses,
+                     int nmass, const ovl_sign* sign, const ovl_lowmodes* lowmodes, double tol, int maxiter,
+                     const ovl_solve_opts* opts, ovl_solve_stats* stats, ovl_stream_t s);
 int ovl_propagator(void* out, const void* x, const ovl_gauge* u, double rho, const ovl_sign* sign,
                    const ovl_lowmodes* lowmodes, ovl_prec prec, int nrhs, ovl_stream_t s);
 

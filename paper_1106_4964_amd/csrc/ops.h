@@ -90,6 +90,9 @@ void overlap_apply(void* out, const void* in, const ovl_gauge* u, double rho, do
 // out = ap in + am gamma5 sign(H_w) in  (the general combine behind D(m))
 void overlap_combine(void* out, const void* in, const ovl_gauge* u, double rho, double ap, double am,
                      const ovl_sign* sg, const ovl_lowmodes* lm, int prec, int nrhs, hipStream_t s);
+// out = ap in + am sign(H_w) gamma5 in
+void overlap_combine_dag(void* out, const void* in, const ovl_gauge* u, double rho, double ap, double am,
+                         const ovl_sign* sg, const ovl_lowmodes* lm, int prec, int nrhs, hipStream_t s);
 
 int cg_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, double m, const ovl_sign* sg,
              const ovl_lowmodes* lm, double tol, int maxiter, const ovl_solve_opts* o, ovl_solve_stats* st,

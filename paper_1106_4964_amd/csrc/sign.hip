@@ -274,6 +274,11 @@ void overlap_combine(void* out, const void* in, const ovl_gauge* u, double rho, 
   overlap_driver(out, in, u, rho, ap, am, sg, lm, 1, prec, nrhs, s);
 }
 
+void overlap_combine_dag(void* out, const void* in, const ovl_gauge* u, double rho, double ap, double am,
+                         const ovl_sign* sg, const ovl_lowmodes* lm, int prec, int nrhs, hipStream_t s) {
+  overlap_driver(out, in, u, rho, ap, am, sg, lm, 2, prec, nrhs, s);
+}
+
 }  // namespace ovl
 
 using namespace ovl;

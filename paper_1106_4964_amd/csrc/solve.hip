@@ -43,6 +43,7 @@ struct Scalars {
   double alpha[2 * OVL_MAX_RHS];   // complex (a, 0)
   double malpha[2 * OVL_MAX_RHS];  // complex (-a, 0)
   double beta[2 * OVL_MAX_RHS];
+  double tcoef[2 * OVL_MAX_RHS];   // weight of the new gradient in p (0 = p frozen)
   double one[2 * OVL_MAX_RHS];
   double mone[2 * OVL_MAX_RHS];
   double scale[2 * OVL_MAX_RHS];   // rhs scale factors of the inner system
@@ -81,24 +82,30 @@ __global__ void alpha_kernel(int R, Scalars* S) {
   S->malpha[2 * r + 1] = 0.0;
 }
 
+// p = tcoef * g + beta * p with g the new gradient.  A rhs that reaches its
+// target takes this step's direction update; from then on p is frozen
+// (tcoef 0, beta 1) while alpha = 0 leaves its iterate alone.
 __global__ void beta_kernel(int R, Scalars* S) {
   const int r = threadIdx.x;
   if (r >= R) return;
-  double b = 0.0;
+  double b = 1.0, tc = 0.0;
   if (S->active[r]) {
     const double rrn = S->rrn[r];
     if (!(rrn == rrn) || isinf(rrn)) {
       S->bad[r] = 2;
       S->active[r] = 0;
+      b = 0.0;
     } else {
       b = rrn / S->rr[r];
+      tc = 1.0;
       S->rr[r] = rrn;
       if (rrn <= S->target[r]) S->active[r] = 0;
     }
   }
-  if (!S->active[r]) b = 0.0;
   S->beta[2 * r] = b;
   S->beta[2 * r + 1] = 0.0;
+  S->tcoef[2 * r] = tc;
+  S->tcoef[2 * r + 1] = 0.0;
 }
 
 struct Solver {
@@ -244,7 +251,7 @@ int cg_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, doub
       S.norm2(rin.p, P, dS->rrn, dS);
       hipLaunchKernelGGL(beta_kernel, dim3(1), dim3(64), 0, s, R, dS);
       S.dm(t.p, rin.p, P, 1, true);
-      blas_axpby(P, t.p, dS->one, P, p.p, dS->beta, S.nsites, R, s);
+      blas_axpby(P, t.p, dS->tcoef, P, p.p, dS->beta, S.nsites, R, s);
     };
 
     // chiral inner iteration: CG on A = P_s D D^dag P_s for y (e64 holds y)
@@ -256,7 +263,7 @@ int cg_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, doub
       blas_axpby(P, q.p, dS->malpha, P, rin.p, dS->one, S.nsites, R, s);
       S.norm2(rin.p, P, dS->rrn, dS);
       hipLaunchKernelGGL(beta_kernel, dim3(1), dim3(64), 0, s, R, dS);
-      blas_axpby(P, rin.p, dS->one, P, p.p, dS->beta, S.nsites, R, s);
+      blas_axpby(P, rin.p, dS->tcoef, P, p.p, dS->beta, S.nsites, R, s);
     };
 
     const double rms_target = P == OVL_F64 ? 1.0 : std::sqrt(12.0 * S.nsites) / 8.0;
@@ -674,6 +681,227 @@ int fgcr_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, do
   return rc;
 }
 
+// Multi-mass CG (eq. 3 and 8).  When sign^2 = 1,
+//   D(m) D(m)^dag = c(m) (K + sigma(m)),  K = gamma5 sign + sign gamma5,
+//   c(m) = rho^2 - m^2/4,  sigma(m) = (2 rho^2 + m^2/2) / c(m),
+// so every mass is a shift of one Hermitian operator.  Stage 1 runs CG on
+// K + sigma_0 (sigma_0 the smallest shift: the lightest mass) and gets the
+// other shifted solutions y_j from the same Krylov space through the
+// shifted-CG recurrences (zeta_j), at the inner precision and to the inner
+// tolerance.  Then x_j = D(m_j)^dag y_j / c_j, and each x_j goes through
+// the FP64 defect-correction loop of cg_solve (which also absorbs the O(delta)
+// difference between D D^dag and c (K + sigma) of the polynomial sign).
+int cg_multimass(void* const* xs, const void* b, int R, const ovl_gauge* u, double rho, const double* masses, int nm,
+                 const ovl_sign* sg, const ovl_lowmodes* lm, double tol, int maxiter, const ovl_solve_opts* o,
+                 ovl_solve_stats* sts, hipStream_t us) {
+  const auto t_start = std::chrono::steady_clock::now();
+  const int P = o ? o->inner_prec : OVL_F64;
+  check_prec(P);
+  const double inner_tol = o ? o->inner_tol : 0.0;
+  const ovl_sign* sg_in = (o && o->inner_sign) ? o->inner_sign : sg;
+  OVL_REQUIRE(sg_in->lam_max == sg->lam_max, OVL_E_ARG, "inner_sign must share lam_max with sign");
+  int recon = 0;
+  (void)gauge_links(u, P, &recon);
+  const ovl_geom* g = &u->geom;
+  const size_t N = static_cast<size_t>(g->N);
+  const size_t v64 = spinor_vec_bytes(g, OVL_F64), vP = spinor_vec_bytes(g, P);
+  const int64_t per_sign_dw_in = 2 * (static_cast<int64_t>(sg_in->c.size()) - 1) + 1;
+  std::vector<double> c(nm), sigma(nm);
+  int base = 0;
+  for (int j = 0; j < nm; ++j) {
+    c[j] = rho * rho - 0.25 * masses[j] * masses[j];
+    sigma[j] = (2.0 * rho * rho + 0.5 * masses[j] * masses[j]) / c[j];
+    if (sigma[j] < sigma[base]) base = j;
+  }
+  for (int j = 0; j < nm; ++j) sts[j] = ovl_solve_stats{};
+  ovl_solve_stats& s0 = sts[base];
+
+  hipStream_t s;
+  OVL_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  hipEvent_t ev;
+  OVL_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  OVL_HIP(hipEventRecord(ev, us));
+  OVL_HIP(hipStreamWaitEvent(s, ev, 0));
+  int its = 0;
+  try {
+    WsBuf r64(v64 * R, s), q64(v64 * R, s), t64(v64 * R, s), pP(vP * R, s), qP(vP * R, s), tP(vP * R, s);
+    WsBuf pj(v64 * R * nm, s), yj(v64 * R * nm, s);
+    WsBuf sc(sizeof(double) * 2 * OVL_MAX_RHS * 4, s);
+    double* dsc = static_cast<double*>(sc.p);
+    auto vec = [&](void* base_, int j) { return static_cast<char*>(base_) + static_cast<size_t>(j) * v64 * R; };
+    std::vector<double> hbuf(2 * OVL_MAX_RHS * 4, 0.0);
+    // four per-rhs complex coefficient rows on the device
+    auto upload = [&](const std::vector<double>& a0, const std::vector<double>& a1, const std::vector<double>& a2,
+                      const std::vector<double>& a3) {
+      std::fill(hbuf.begin(), hbuf.end(), 0.0);
+      for (int r = 0; r < R; ++r) {
+        hbuf[2 * r] = a0[r];
+        hbuf[2 * OVL_MAX_RHS + 2 * r] = a1[r];
+        hbuf[4 * OVL_MAX_RHS + 2 * r] = a2[r];
+        hbuf[6 * OVL_MAX_RHS + 2 * r] = a3[r];
+      }
+      OVL_HIP(hipMemcpyAsync(dsc, hbuf.data(), sizeof(double) * hbuf.size(), hipMemcpyHostToDevice, s));
+      OVL_HIP(hipStreamSynchronize(s));
+    };
+    const double* A0 = dsc;
+    const double* A1 = dsc + 2 * OVL_MAX_RHS;
+    const double* A2 = dsc + 4 * OVL_MAX_RHS;
+    const double* A3 = dsc + 6 * OVL_MAX_RHS;
+    WsBuf red(sizeof(double) * 2 * OVL_MAX_RHS, s);
+    auto reduce = [&](const void* x1, const void* x2) {  // Re x1^dag x2 per rhs (x2 null: norm^2)
+      if (x2)
+        blas_dot(OVL_F64, v64 / 16, x1, x2, R, v64, static_cast<double*>(red.p), s);
+      else
+        blas_norm2(OVL_F64, v64 / 16, x1, R, v64, static_cast<double*>(red.p), s);
+      std::vector<double> h(2 * R);
+      OVL_HIP(hipMemcpyAsync(h.data(), red.p, sizeof(double) * 2 * R, hipMemcpyDeviceToHost, s));
+      OVL_HIP(hipStreamSynchronize(s));
+      std::vector<double> out(R);
+      for (int r = 0; r < R; ++r) out[r] = h[2 * r];
+      return out;
+    };
+    const std::vector<double> ones(R, 1.0), zeros(R, 0.0);
+    // r = b, p_j = b, y_j = 0
+    upload(ones, zeros, zeros, zeros);
+    blas_axpby(OVL_F64, b, A0, OVL_F64, r64.p, nullptr, N, R, s);
+    for (int j = 0; j < nm; ++j) {
+      blas_axpby(OVL_F64, b, A0, OVL_F64, vec(pj.p, j), nullptr, N, R, s);
+      blas_zero(vec(yj.p, j), v64 * R, s);
+    }
+    std::vector<double> bn2 = reduce(b, nullptr), rr = bn2;
+    for (int r = 0; r < R; ++r) OVL_REQUIRE(std::isfinite(bn2[r]), OVL_E_NAN, "right-hand side contains NaN or Inf");
+    const double rel = std::max(0.5 * tol, P == OVL_F64 ? 0.0 : inner_tol);
+    std::vector<std::vector<double>> zeta(nm, std::vector<double>(R, 1.0)), zeta_p = zeta;
+    std::vector<std::vector<int>> act(nm, std::vector<int>(R, 1));
+    for (int j = 0; j < nm; ++j)
+      for (int r = 0; r < R; ++r) act[j][r] = bn2[r] > 0.0;
+    std::vector<double> alpha_p(R, 1.0), beta_p(R, 0.0);
+    while (its < maxiter) {
+      std::vector<int> live(R, 0);
+      bool any = false;
+      for (int r = 0; r < R; ++r)
+        for (int j = 0; j < nm; ++j)
+          if (act[j][r]) live[r] = 1;
+      for (int r = 0; r < R; ++r) any = any || live[r];
+      if (!any) break;
+      // q = (K + sigma_0) p_0 at the inner precision
+      void* p0 = vec(pj.p, base);
+      blas_convert(OVL_F64, p0, P, pP.p, N, R, s);
+      overlap_combine(qP.p, pP.p, u, rho, sigma[base], 1.0, sg_in, lm, P, R, s);
+      overlap_combine_dag(tP.p, pP.p, u, rho, 0.0, 1.0, sg_in, lm, P, R, s);
+      blas_convert(P, qP.p, OVL_F64, q64.p, N, R, s);
+      blas_convert(P, tP.p, OVL_F64, t64.p, N, R, s);
+      upload(ones, ones, zeros, zeros);
+      blas_axpby(OVL_F64, t64.p, A0, OVL_F64, q64.p, A1, N, R, s);
+      s0.sign_applies += 2 * R;
+      s0.dslash_applies += 2 * R * per_sign_dw_in;
+      const std::vector<double> pq = reduce(p0, q64.p);
+      std::vector<double> alpha(R, 0.0);
+      for (int r = 0; r < R; ++r) {
+        if (!live[r]) continue;
+        OVL_REQUIRE(std::isfinite(pq[r]), OVL_E_NAN, "NaN or Inf in a multi-mass CG iterate");
+        OVL_REQUIRE(pq[r] > 0.0, OVL_E_BREAKDOWN, "multi-mass CG breakdown: p^dag A p <= 0");
+        alpha[r] = rr[r] / pq[r];
+      }
+      // shifted coefficients
+      std::vector<std::vector<double>> zn = zeta, aj(nm, std::vector<double>(R, 0.0));
+      for (int j = 0; j < nm; ++j)
+        for (int r = 0; r < R; ++r) {
+          if (!live[r]) continue;
+          if (j == base) {
+            zn[j][r] = 1.0;
+            aj[j][r] = alpha[r];
+            continue;
+          }
+          const double d = sigma[j] - sigma[base];
+          const double z = zeta[j][r], zp = zeta_p[j][r];
+          const double den = alpha[r] * beta_p[r] * (zp - z) + zp * alpha_p[r] * (1.0 + d * alpha[r]);
+          zn[j][r] = (den != 0.0) ? z * zp * alpha_p[r] / den : 0.0;
+          aj[j][r] = (z != 0.0) ? alpha[r] * zn[j][r] / z : 0.0;
+        }
+      // y_j += alpha_j p_j (active shifts only)
+      for (int j = 0; j < nm; ++j) {
+        std::vector<double> a(R, 0.0);
+        for (int r = 0; r < R; ++r) a[r] = act[j][r] ? aj[j][r] : 0.0;
+        upload(a, ones, zeros, zeros);
+        blas_axpby(OVL_F64, vec(pj.p, j), A0, OVL_F64, vec(yj.p, j), A1, N, R, s);
+      }
+      // r -= alpha q
+      std::vector<double> ma(R);
+      for (int r = 0; r < R; ++r) ma[r] = -alpha[r];
+      upload(ma, ones, zeros, zeros);
+      blas_axpby(OVL_F64, q64.p, A0, OVL_F64, r64.p, A1, N, R, s);
+      const std::vector<double> rrn = reduce(r64.p, nullptr);
+      std::vector<double> beta(R, 0.0);
+      for (int r = 0; r < R; ++r) {
+        if (!live[r]) continue;
+        OVL_REQUIRE(std::isfinite(rrn[r]), OVL_E_NAN, "NaN or Inf in a multi-mass CG iterate");
+        beta[r] = rrn[r] / rr[r];
+      }
+      // p_j = zeta_j r + beta_j p_j (frozen for finished shifts)
+      for (int j = 0; j < nm; ++j) {
+        std::vector<double> zc(R, 0.0), bc(R, 1.0);
+        for (int r = 0; r < R; ++r) {
+          if (!live[r] || !act[j][r]) continue;
+          const double ratio = (zeta[j][r] != 0.0) ? zn[j][r] / zeta[j][r] : 0.0;
+          zc[r] = zn[j][r];
+          bc[r] = beta[r] * ratio * ratio;
+        }
+        upload(zc, bc, zeros, zeros);
+        blas_axpby(OVL_F64, r64.p, A0, OVL_F64, vec(pj.p, j), A1, N, R, s);
+      }
+      ++its;
+      for (int r = 0; r < R; ++r) {
+        if (!live[r]) continue;
+        for (int j = 0; j < nm; ++j) {
+          zeta_p[j][r] = zeta[j][r];
+          zeta[j][r] = zn[j][r];
+          // residual of shift j is zeta_j r
+          if (act[j][r] && std::fabs(zeta[j][r]) * std::sqrt(rrn[r]) <= rel * std::sqrt(bn2[r])) act[j][r] = 0;
+        }
+        alpha_p[r] = alpha[r];
+        beta_p[r] = beta[r];
+        rr[r] = rrn[r];
+      }
+      if (log_on() && its % 100 == 0) fprintf(stderr, "[ovl multimass] iteration %d\n", its);
+    }
+    // x_j = D(m_j)^dag y_j / c_j in FP64
+    for (int j = 0; j < nm; ++j) {
+      overlap_apply(t64.p, vec(yj.p, j), u, rho, masses[j], sg, lm, 2, OVL_F64, R, s);
+      std::vector<double> ic(R, 1.0 / c[j]);
+      upload(ic, zeros, zeros, zeros);
+      blas_axpby(OVL_F64, t64.p, A0, OVL_F64, xs[j], nullptr, N, R, s);
+    }
+    OVL_HIP(hipStreamSynchronize(s));
+  } catch (...) {
+    (void)hipStreamSynchronize(s);
+    (void)hipEventDestroy(ev);
+    (void)hipStreamDestroy(s);
+    throw;
+  }
+  OVL_HIP(hipEventRecord(ev, s));
+  OVL_HIP(hipStreamWaitEvent(us, ev, 0));
+  OVL_HIP(hipStreamSynchronize(s));
+  OVL_HIP(hipEventDestroy(ev));
+  OVL_HIP(hipStreamDestroy(s));
+  const double t_shift = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  if (log_on()) fprintf(stderr, "[ovl multimass] shifted CG: %d iterations, %.2f s\n", its, t_shift);
+  // FP64 defect correction per mass from x_j
+  int rc = OVL_OK;
+  for (int j = 0; j < nm; ++j) {
+    ovl_solve_stats cs{};
+    const int r_j = cg_solve(xs[j], b, R, u, rho, masses[j], sg, lm, tol, std::max(0, maxiter - its), o, &cs, us);
+    if (r_j != OVL_OK) rc = r_j;
+    const int64_t sa = sts[j].sign_applies, da = sts[j].dslash_applies;
+    sts[j] = cs;
+    sts[j].sign_applies += sa;
+    sts[j].dslash_applies += da;
+  }
+  sts[base].iterations += its;
+  sts[base].seconds += t_shift;
+  return rc;
+}
+
 }  // namespace ovl
 
 using namespace ovl;
@@ -709,6 +937,28 @@ int ovl_fgcr_solve(void* x, const void* b, int nrhs, const ovl_gauge* u, double 
     *stats = ovl_solve_stats{};
     return fgcr_solve(x, b, nrhs, u, rho, m, sign, lowmodes, M, restart, tol, maxiter, opts, stats,
                       static_cast<hipStream_t>(s));
+  });
+}
+
+int ovl_cg_multimass(void* const* x, const void* b, int nrhs, const ovl_gauge* u, double rho, const double* masses,
+                     int nmass, const ovl_sign* sign, const ovl_lowmodes* lowmodes, double tol, int maxiter,
+                     const ovl_solve_opts* opts, ovl_solve_stats* stats, ovl_stream_t s) {
+  return guard([&] {
+    OVL_REQUIRE(x && b && u && sign && stats && masses, OVL_E_ARG, "null argument");
+    OVL_REQUIRE(nmass >= 1 && nmass <= 8, OVL_E_ARG, "cg_multimass: 1 <= nmass <= 8");
+    OVL_REQUIRE(nrhs >= 1 && nrhs <= OVL_MAX_RHS, OVL_E_ARG, "cg_multimass: 1 <= nrhs <= 12");
+    OVL_REQUIRE(tol > 0.0 && maxiter >= 0, OVL_E_ARG, "need tol > 0 and maxiter >= 0");
+    for (int j = 0; j < nmass; ++j) {
+      OVL_REQUIRE(x[j] && x[j] != b, OVL_E_ALIAS, "each x_j must be a separate buffer, not b");
+      for (int k = 0; k < j; ++k) OVL_REQUIRE(x[k] != x[j], OVL_E_ALIAS, "x buffers must differ");
+      OVL_REQUIRE(masses[j] > -2.0 * rho && masses[j] < 2.0 * rho, OVL_E_ARG, "need |m| < 2 rho");
+    }
+    OVL_REQUIRE(!(opts && opts->chiral), OVL_E_ARG, "cg_multimass: chiral mode not supported");
+    OVL_REQUIRE(!(opts && opts->harvest_x && opts->harvest_b && opts->harvest_cap > 0), OVL_E_ARG,
+                "cg_multimass: no harvesting");
+    if (lowmodes && lowmodes->ell == 0) lowmodes = nullptr;
+    return cg_multimass(x, b, nrhs, u, rho, masses, nmass, sign, lowmodes, tol, maxiter, opts, stats,
+                        static_cast<hipStream_t>(s));
   });
 }
 

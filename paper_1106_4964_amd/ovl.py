@@ -146,6 +146,7 @@ _SIGS = {
     "ovl_sign_apply": (P, P, P, D, P, P, I, I, ST),
     "ovl_overlap_apply": (P, P, P, D, D, P, P, I, I, I, ST),
     "ovl_cg_solve": (P, P, I, P, D, D, P, P, D, I, P, P, ST),
+    "ovl_cg_multimass": (P, P, I, P, D, P, I, P, P, D, I, P, P, ST),
     "ovl_propagator": (P, P, P, D, P, P, I, I, ST),
     "ovl_counters": (P, P, I),
     "ovl_stencil_tune": (I,),

@@ -260,6 +260,44 @@ def test_cg_chiral_refuses_harvest(c1):
     assert e.value.name == "OVL_E_ARG"
 
 
+@pytest.mark.parametrize("prec", [ovl.OVL_F64, ovl.OVL_F32])
+def test_cg_multimass(c1, c1_lowmodes, prec):
+    """Three masses from one shifted Krylov space, each finished by the FP64
+    defect correction: every x_j reaches 1e-10 judged by the oracle, in fewer
+    sign applications than three separate solves."""
+    V, lam = c1_lowmodes
+    g = ovl.Geometry(c1["dims"])
+    gauge = gu.make_gauge(g, c1["U"], [] if prec == ovl.OVL_F64 else [(prec, 1)])
+    lm = ovl.LowModes(g, gu.pack(g, V, ovl.OVL_F64, len(V)), lam)
+    s = ovl.Sign(abs(lam[-1]), c1["hi"], delta=1e-12)
+    so = sign.SignApprox(lam_max=c1["hi"], eps=s.eps, coeffs=s.coeffs())
+    b = si.point_sources(c1["dims"])
+    masses = np.array([0.05, 0.01, 0.2])
+    inner_tol = 0.0 if prec == ovl.OVL_F64 else 1e-5
+    opts = ovl.SolveOpts(prec, inner_tol, 0, 1, 60)
+    xs = [gu.pack(g, np.zeros_like(b), ovl.OVL_F64, 12) for _ in masses]
+    ptrs = (ctypes.c_void_p * 3)(*[x.data_ptr() for x in xs])
+    sts = (ovl.SolveStats * 3)()
+    rc = ovl.ovl_cg_multimass(ptrs, gu.pack(g, b, ovl.OVL_F64, 12), 12, gauge, RHO, masses, 3, s, lm, 1e-10, 5000,
+                              opts, sts, None)
+    assert rc == 0
+    multi = sum(st.sign_applies for st in sts)
+    for j, m in enumerate(masses):
+        x = gu.unpack(g, xs[j], ovl.OVL_F64, 12)
+        assert max(sts[j].true_residual[:12]) <= 1e-10
+        for r in (0, 9):
+            res = b[r] - sign.overlap_apply(c1["lat"], c1["U"], x[r], RHO, m, so, V, lam)
+            assert np.linalg.norm(res) / np.linalg.norm(b[r]) <= 1.05e-10
+    single = 0
+    for m in masses:
+        rc, _, st = _solve_opts(g, gauge, s, lm, b, m, opts)
+        assert rc == 0
+        single += st.sign_applies
+    print("sign applications: multi-mass %d (iterations %s), separate %d"
+          % (multi, [st.iterations for st in sts], single))
+    assert multi < single
+
+
 def test_cg_batch_equals_single(c1, c1_lowmodes):
     V, lam = c1_lowmodes
     g = ovl.Geometry(c1["dims"])

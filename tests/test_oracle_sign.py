@@ -189,6 +189,27 @@ def test_chiral_sector_operator(small, chir):
     assert np.linalg.norm(lhs - Ps @ lhs) < 1e-12 * np.linalg.norm(lhs)
 
 
+@pytest.mark.parametrize("m", [0.01, 0.05, 0.3])
+def test_mass_shift_structure(small, m):
+    """With the exact sign, D(m) D(m)^dag = (rho^2 - m^2/4) (K + sigma(m))
+    with the mass-independent K = gamma5 sign + sign gamma5 and
+    sigma(m) = (2 rho^2 + m^2/2) / (rho^2 - m^2/4) (eq. 3 and 8): every mass
+    is a shift of one operator, so one Krylov space serves them all."""
+    lat, U, H, lo, hi = small
+    rho = 1.5
+    n = H.shape[0]
+    G5 = dense.dense_gamma5(lat)
+    E = dense.exact_sign(H)
+    Dm = (rho + m / 2) * np.eye(n) + (rho - m / 2) * G5 @ E
+    K = G5 @ E + E @ G5
+    sigma = (2 * rho * rho + m * m / 2) / (rho * rho - m * m / 4)
+    lhs = Dm @ Dm.conj().T
+    rhs = (rho * rho - m * m / 4) * (K + sigma * np.eye(n))
+    assert np.max(np.abs(lhs - rhs)) < 1e-12 * np.max(np.abs(lhs))
+    # K + sigma is positive: K's spectrum lies in [-2, 2] and sigma > 2
+    assert np.max(np.linalg.eigvalsh(K)) <= 2 + 1e-12 and sigma > 2
+
+
 def test_free_field_overlap_closed_form():
     """U = 1: D(p) = 1 + (M(p) + i gamma.sin p)/omega(p), M = -rho + sum(1-cos p)."""
     lat = Lattice((4, 4, 2, 2))
