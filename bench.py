@@ -62,7 +62,7 @@ def parse():
     ap.add_argument("--prec", type=str, default="f16")
     ap.add_argument("--no-cg", action="store_true")
     ap.add_argument("--cg-masses", type=str, default="0.01")
-    ap.add_argument("--inner-delta", type=float, default=1e-4,
+    ap.add_argument("--inner-delta", type=float, default=1e-3,
                     help="sign accuracy of the inner (low-precision) operator; 0 = same as outer")
     ap.add_argument("--inner-tol", type=float, default=1e-3)
     ap.add_argument("--graph-chunk", type=int, default=8)
