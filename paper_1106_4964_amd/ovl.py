@@ -13,6 +13,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import sys
 
 import numpy as np
 
@@ -270,9 +271,13 @@ class Geometry:
         ovl_geom_eo_index(self.handle, c, ctypes.byref(e))
         return e.value
 
-    def __del__(self):
+    def __del__(self, _lib=lib, _exiting=sys.is_finalizing):
+        # at interpreter exit module globals may be gone and the process end
+        # releases the device memory anyway
+        if _exiting():
+            return
         if getattr(self, "handle", None) is not None and self.handle.value:
-            lib.ovl_geom_destroy(self.handle)
+            _lib.ovl_geom_destroy(self.handle)
             self.handle = None
 
 
@@ -292,9 +297,13 @@ class Gauge:
     def set_repr(self, prec, compress12, stream=None):
         ovl_gauge_set_repr(self.handle, prec, int(compress12), stream)
 
-    def __del__(self):
+    def __del__(self, _lib=lib, _exiting=sys.is_finalizing):
+        # at interpreter exit module globals may be gone and the process end
+        # releases the device memory anyway
+        if _exiting():
+            return
         if getattr(self, "handle", None) is not None and self.handle.value:
-            lib.ovl_gauge_destroy(self.handle)
+            _lib.ovl_gauge_destroy(self.handle)
             self.handle = None
 
 
@@ -315,9 +324,13 @@ class Sign:
         ovl_sign_coeffs(self.handle, c, self.n + 1)
         return c
 
-    def __del__(self):
+    def __del__(self, _lib=lib, _exiting=sys.is_finalizing):
+        # at interpreter exit module globals may be gone and the process end
+        # releases the device memory anyway
+        if _exiting():
+            return
         if getattr(self, "handle", None) is not None and self.handle.value:
-            lib.ovl_sign_destroy(self.handle)
+            _lib.ovl_sign_destroy(self.handle)
             self.handle = None
 
 
@@ -332,9 +345,13 @@ class LowModes:
         self.V = V_dev  # keep the borrowed buffer alive
         self.ell = len(lam)
 
-    def __del__(self):
+    def __del__(self, _lib=lib, _exiting=sys.is_finalizing):
+        # at interpreter exit module globals may be gone and the process end
+        # releases the device memory anyway
+        if _exiting():
+            return
         if getattr(self, "handle", None) is not None and self.handle.value:
-            lib.ovl_lowmodes_destroy(self.handle)
+            _lib.ovl_lowmodes_destroy(self.handle)
             self.handle = None
 
 
@@ -359,9 +376,13 @@ class Net:
         ovl_net_get_weights(self.handle, w1, w2)
         return w1, w2
 
-    def __del__(self):
+    def __del__(self, _lib=lib, _exiting=sys.is_finalizing):
+        # at interpreter exit module globals may be gone and the process end
+        # releases the device memory anyway
+        if _exiting():
+            return
         if getattr(self, "handle", None) is not None and self.handle.value:
-            lib.ovl_net_destroy(self.handle)
+            _lib.ovl_net_destroy(self.handle)
             self.handle = None
 
 
