@@ -505,6 +505,14 @@ def main():
                 cg["note"] = ("plain FP64 time measured on %d of the 12 point sources and scaled by 12/%d "
                               "(FP64 solves gain nothing from batching)" % (nfp, nfp))
 
+    lib_live, lib_peak = ctypes.c_int64(), ctypes.c_int64()
+    ovl.ovl_mem_stats(ctypes.byref(lib_live), ctypes.byref(lib_peak), 0)
+    memory = {"library_peak_GB": round(lib_peak.value / 1e9, 2),
+              "torch_peak_GB": round(torch.cuda.max_memory_allocated() / 1e9, 2),
+              "note": "library: workspace pool, eigensolver basis and packed links; torch: fields and the "
+                      "eigenvectors; the high-water mark is at most their sum"}
+    log("device memory: %s" % memory)
+
     cpu = None
     if not args.no_cpu:
         log("cpu baseline (oracle)")
@@ -535,6 +543,7 @@ def main():
         "cpu_baseline": cpu,
         "dslash": dslash,
         "cg": cg,
+        "memory": memory,
     }
     print(json.dumps(out), flush=True)
 

@@ -329,7 +329,9 @@ int ovl_propagator(void* out, const void* x, const ovl_gauge* u, double rho, con
  *   their eigenvalues.  Stops when every wanted pair has
  *   ||H_w v - lambda v|| <= tol * lam_max, or after max_iter restart cycles
  *   (OVL_W_NOT_CONVERGED).  lam_max must bound |spectrum(H_w)|.  Device
- *   workspace: K + 5 FP64 spinors, K = max(2 want, want + 40) <= 512.
+ *   workspace: K + 5 FP64 spinors, K = max(2 want, want + 40) <= 512
+ *   (want = ell + max(8, ell/10)), lowered in steps of 8 toward want + 40
+ *   while the workspace would exceed 90% of the free device memory.
  */
 typedef struct {
   int iterations;      /* restart cycles                              */
@@ -426,6 +428,14 @@ int ovl_stencil_timer_read(ovl_prec prec, int compress12, int nextra, int nrhs, 
  * the host since the last reset (graph replays are not seen here).
  */
 int ovl_counters(int64_t* stencil_launches, int64_t* stencil_vectors, int reset);
+
+/* ovl_mem_stats: device memory held by the library (workspace pool, which
+ * keeps released buffers for reuse until the process ends; eigensolver
+ * basis; packed links) now and at its peak since the last reset_peak; the
+ * caller's own buffers (fields, borrowed eigenvectors) are not counted.
+ * Either pointer may be NULL.
+ */
+int ovl_mem_stats(int64_t* live_bytes, int64_t* peak_bytes, int reset_peak);
 
 #ifdef __cplusplus
 }

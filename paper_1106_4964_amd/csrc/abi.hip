@@ -36,6 +36,21 @@ void set_last_error(const std::string& msg) { g_last_error = msg; }
 
 namespace {
 std::atomic<int64_t> g_stencil_launches{0}, g_stencil_vectors{0};
+std::atomic<int64_t> g_mem_live{0}, g_mem_peak{0};
+}
+bool log_on() {
+  static const bool on = [] {
+    const char* e = std::getenv("OVL_LOG");
+    return e && *e && *e != '0';
+  }();
+  return on;
+}
+
+void mem_track(int64_t delta) {
+  const int64_t now = g_mem_live.fetch_add(delta) + delta;
+  int64_t pk = g_mem_peak.load();
+  while (now > pk && !g_mem_peak.compare_exchange_weak(pk, now)) {
+  }
 }
 void count_stencil(int nrhs) {
   g_stencil_launches.fetch_add(1, std::memory_order_relaxed);
@@ -58,6 +73,7 @@ void* ws_get(size_t bytes, hipStream_t s) {
     (void)hipGetLastError();
     throw Error(OVL_E_NOMEM, "device workspace allocation of " + std::to_string(bytes) + " bytes failed");
   }
+  mem_track(static_cast<int64_t>(bytes));
   std::lock_guard<std::mutex> lk(P.mu);
   P.sizes[p] = bytes;
   return p;
@@ -147,6 +163,13 @@ int ovl_counters(int64_t* stencil_launches, int64_t* stencil_vectors, int reset)
     g_stencil_launches = 0;
     g_stencil_vectors = 0;
   }
+  return OVL_OK;
+}
+
+int ovl_mem_stats(int64_t* live_bytes, int64_t* peak_bytes, int reset_peak) {
+  if (live_bytes) *live_bytes = g_mem_live.load();
+  if (peak_bytes) *peak_bytes = g_mem_peak.load();
+  if (reset_peak) g_mem_peak = g_mem_live.load();
   return OVL_OK;
 }
 

@@ -578,6 +578,12 @@ namespace ovl {
 // while earlier kernels that used it are still running.
 void* ws_get(size_t bytes, hipStream_t s);
 void ws_put(void* p, hipStream_t s);
+// Accounting of the device memory the library holds (workspace pool,
+// eigensolver buffers, packed links): +bytes on allocation, -bytes on free.
+void mem_track(int64_t delta);
+// OVL_LOG=1 in the environment: the solvers print one line per outer cycle
+// (and the CG every 100 inner iterations) on stderr.
+bool log_on();
 
 struct WsBuf {
   void* p = nullptr;

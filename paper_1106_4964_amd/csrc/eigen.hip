@@ -22,6 +22,7 @@
 #include <chrono>
 #include <cmath>
 #include <complex>
+#include <cstdio>
 #include <numeric>
 
 #include "ops.h"
@@ -136,14 +137,19 @@ struct Hw {
 
 struct DevMem {
   void* p = nullptr;
-  explicit DevMem(size_t bytes) {
+  size_t n = 0;
+  explicit DevMem(size_t bytes) : n(bytes) {
     if (hipMalloc(&p, bytes) != hipSuccess) {
       (void)hipGetLastError();
       throw Error(OVL_E_NOMEM, "eigensolver: device allocation of " + std::to_string(bytes) + " bytes failed");
     }
+    mem_track(static_cast<int64_t>(n));
   }
   ~DevMem() {
-    if (p) (void)hipFree(p);
+    if (p) {
+      (void)hipFree(p);
+      mem_track(-static_cast<int64_t>(n));
+    }
   }
   DevMem(const DevMem&) = delete;
   DevMem& operator=(const DevMem&) = delete;
@@ -290,11 +296,22 @@ int ovl_hw_eigs(const ovl_gauge* u, double rho, int ell, int m, void* V, double*
     OVL_REQUIRE(lam_max > 0.0 && tol > 0.0 && max_iter >= 1 && degree >= 1, OVL_E_ARG, "bad eigensolver parameter");
     const int want = ell + std::max(8, ell / 10);  // cushion: a +-lambda pair may straddle the cut
     OVL_REQUIRE(ell >= 1 && m >= want, OVL_E_ARG, "need m >= ell + max(8, ell/10) vectors in V");
-    const int K = std::min(512, std::max(2 * want, want + 40));  // Lanczos basis
-    const int keep = want + (K - want) / 2;                     // thick-restart size
+    // Lanczos basis: 2 want (at least want + 40, at most 512) vectors, cut
+    // back toward want + 40 while the basis and its work vectors would take
+    // more than 90% of the free device memory (large volumes with many modes)
+    int K = std::min(512, std::max(2 * want, want + 40));
     const auto t0 = std::chrono::steady_clock::now();
     hipStream_t s = static_cast<hipStream_t>(st);
     const ovl_geom* g = &u->geom;
+    {
+      size_t fr = 0, tot = 0;
+      OVL_HIP(hipMemGetInfo(&fr, &tot));
+      const size_t vb = spinor_vec_bytes(g, OVL_F64);
+      auto need = [&](int k) { return vb * (k + 5) + sizeof(double2) * static_cast<size_t>(k) * k; };
+      while (K > want + 40 && static_cast<double>(need(K)) > 0.9 * static_cast<double>(fr)) K -= 8;
+      K = std::max(K, std::min(512, want + 40));
+    }
+    const int keep = want + (K - want) / 2;  // thick-restart size
     Hw H{u, rho, s, spinor_vec_bytes(g, OVL_F64), nullptr, 0};
     H.links = gauge_links(u, OVL_F64, &H.recon);
     const size_t v64 = H.v64;
@@ -398,6 +415,7 @@ int ovl_hw_eigs(const ovl_gauge* u, double rho, int ell, int m, void* V, double*
       // the wanted block must stand clear of the damped band [-1, 1]
       if (th[want - 1] < 1.5 && cycle < max_iter) {
         cut *= 1.4;
+        if (log_on()) fprintf(stderr, "[ovl eigs] cycle %d (basis %d): widening the damped band\n", cycle, K);
         // restart from the sum of the current top Ritz vectors
         upload_S(Sd, K, K);
         block_rotate_inplace(g, Q.p, K, static_cast<const double2*>(Sdev.p), 1, s);
@@ -451,6 +469,9 @@ int ovl_hw_eigs(const ovl_gauge* u, double rho, int ell, int m, void* V, double*
       }
       stats->iterations = cycle + 1;
       stats->max_residual = worst;
+      if (log_on())
+        fprintf(stderr, "[ovl eigs] cycle %d (basis %d): max residual %.3e, target %.3e\n", cycle, K, worst,
+                tol * lam_max);
       if (worst <= tol * lam_max || cycle + 1 >= max_iter) break;
       // thick restart: keep the top `keep` Ritz vectors of B and the residual direction
       upload_S(Sd, K, K);

@@ -231,6 +231,7 @@ double su3_deviation(const ovl_gauge* u, hipStream_t s) {
 void gauge_create_master(ovl_gauge* u, const double* aos, hipStream_t s) {
   const ovl_geom* g = &u->geom;
   OVL_HIP(hipMalloc(&u->master, link_bytes(g, OVL_F64, 18)));
+  mem_track(static_cast<int64_t>(link_bytes(g, OVL_F64, 18)));
   gauge_pack<OVL_F64, 18>(g->geo, reinterpret_cast<const double2*>(aos), u->master, s);
   OVL_HIP(hipStreamSynchronize(s));
   u->links[OVL_F64] = u->master;
@@ -247,13 +248,17 @@ void repack(const Geo& g, const void* master, void* dst, hipStream_t s) {
 void gauge_set_repr(ovl_gauge* u, int prec, int recon, hipStream_t s) {
   const ovl_geom* g = &u->geom;
   if (prec == OVL_F64 && recon == 18) {
-    if (u->links[OVL_F64] && u->links[OVL_F64] != u->master) OVL_HIP(hipFree(u->links[OVL_F64]));
+    if (u->links[OVL_F64] && u->links[OVL_F64] != u->master) {
+      OVL_HIP(hipFree(u->links[OVL_F64]));
+      mem_track(-static_cast<int64_t>(link_bytes(g, OVL_F64, u->recon[OVL_F64])));
+    }
     u->links[OVL_F64] = u->master;
     u->recon[OVL_F64] = 18;
     return;
   }
   void* dst = nullptr;
   OVL_HIP(hipMalloc(&dst, link_bytes(g, prec, recon)));
+  mem_track(static_cast<int64_t>(link_bytes(g, prec, recon)));
   try {
     const bool r18 = recon == 18;
     switch (prec) {
@@ -265,17 +270,28 @@ void gauge_set_repr(ovl_gauge* u, int prec, int recon, hipStream_t s) {
     OVL_HIP(hipStreamSynchronize(s));
   } catch (...) {
     (void)hipFree(dst);
+    mem_track(-static_cast<int64_t>(link_bytes(g, prec, recon)));
     throw;
   }
-  if (u->links[prec] && u->links[prec] != u->master) OVL_HIP(hipFree(u->links[prec]));
+  if (u->links[prec] && u->links[prec] != u->master) {
+    OVL_HIP(hipFree(u->links[prec]));
+    mem_track(-static_cast<int64_t>(link_bytes(g, prec, u->recon[prec])));
+  }
   u->links[prec] = dst;
   u->recon[prec] = recon;
 }
 
 void gauge_free(ovl_gauge* u) {
+  const ovl_geom* g = &u->geom;
   for (int p = 0; p < 4; ++p)
-    if (u->links[p] && u->links[p] != u->master) (void)hipFree(u->links[p]);
-  if (u->master) (void)hipFree(u->master);
+    if (u->links[p] && u->links[p] != u->master) {
+      (void)hipFree(u->links[p]);
+      mem_track(-static_cast<int64_t>(link_bytes(g, p, u->recon[p])));
+    }
+  if (u->master) {
+    (void)hipFree(u->master);
+    mem_track(-static_cast<int64_t>(link_bytes(g, OVL_F64, 18)));
+  }
 }
 
 const void* gauge_links(const ovl_gauge* u, int prec, int* recon) {

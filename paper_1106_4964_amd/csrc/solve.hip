@@ -24,16 +24,6 @@
 namespace ovl {
 namespace {
 
-// OVL_LOG=1 in the environment: one line per outer cycle and every 100
-// inner iterations on stderr (residual history of a running solve).
-bool log_on() {
-  static const bool on = [] {
-    const char* e = std::getenv("OVL_LOG");
-    return e && *e && *e != '0';
-  }();
-  return on;
-}
-
 // Scalars of one inner solve, all device-resident, one slot per rhs.
 struct Scalars {
   double rr[OVL_MAX_RHS];

@@ -150,6 +150,7 @@ _SIGS = {
     "ovl_cg_multimass": (P, P, I, P, D, P, I, P, P, D, I, P, P, ST),
     "ovl_propagator": (P, P, P, D, P, P, I, I, ST),
     "ovl_counters": (P, P, I),
+    "ovl_mem_stats": (P, P, I),
     "ovl_stencil_tune": (I,),
     "ovl_stencil_timer": (I,),
     "ovl_stencil_timer_read": (I, I, I, I, P, P),
