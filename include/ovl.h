@@ -433,7 +433,8 @@ int ovl_counters(int64_t* stencil_launches, int64_t* stencil_vectors, int reset)
  * keeps released buffers for reuse until the process ends; eigensolver
  * basis; packed links) now and at its peak since the last reset_peak; the
  * caller's own buffers (fields, borrowed eigenvectors) are not counted.
- * Either pointer may be NULL.
+ * Either pointer may be NULL; with reset_peak the values returned are those
+ * before the reset.
  */
 int ovl_mem_stats(int64_t* live_bytes, int64_t* peak_bytes, int reset_peak);
 

@@ -219,3 +219,29 @@ def test_every_pinned_shape(prec):
                 ovl.stencil_set_shape(g, prec, c12, 0, 12, bad)
     finally:
         ovl.ovl_stencil_tune(1)
+
+
+def test_mem_stats_counts_links():
+    """The library's device-memory accounting follows the packed links: the
+    FP64 master copy (18 reals of 8 bytes per link) plus an F16 12-real copy
+    (2 bytes per real), and both are returned when the gauge is destroyed."""
+    dims = (4, 4, 4, 6)
+    g = ovl.Geometry(dims)
+    U = si.gauge_field(dims, 0.25, 8)
+    # a first gauge leaves the workspace buffers its checks use in the pool
+    del_me = gu.make_gauge(g, U, [(ovl.OVL_F16, 1)])
+    del del_me
+    live, peak = ctypes.c_int64(), ctypes.c_int64()
+    ovl.ovl_mem_stats(None, None, 1)  # peak := live
+    ovl.ovl_mem_stats(ctypes.byref(live), ctypes.byref(peak), 0)
+    live0 = live.value
+    assert peak.value == live0
+    gauge = gu.make_gauge(g, U, [(ovl.OVL_F16, 1)])
+    ovl.ovl_mem_stats(ctypes.byref(live), ctypes.byref(peak), 0)
+    links = 4 * g.N * (18 * 8 + 12 * 2)
+    assert live.value - live0 == links
+    assert peak.value >= live.value
+    del gauge
+    ovl.ovl_mem_stats(ctypes.byref(live), ctypes.byref(peak), 0)
+    assert live.value == live0
+    assert peak.value >= live0 + links
