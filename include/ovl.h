@@ -331,7 +331,8 @@ int ovl_propagator(void* out, const void* x, const ovl_gauge* u, double rho, con
  *   (OVL_W_NOT_CONVERGED).  lam_max must bound |spectrum(H_w)|.  Device
  *   workspace: K + 5 FP64 spinors, K = max(2 want, want + 40) <= 512
  *   (want = ell + max(8, ell/10)), lowered in steps of 8 toward want + 40
- *   while the workspace would exceed 90% of the free device memory.
+ *   while the workspace would exceed 90% of the free device memory;
+ *   OVL_E_ARG when want + 40 > 512 (ell > 429).
  */
 typedef struct {
   int iterations;      /* restart cycles                              */

@@ -296,6 +296,7 @@ int ovl_hw_eigs(const ovl_gauge* u, double rho, int ell, int m, void* V, double*
     OVL_REQUIRE(lam_max > 0.0 && tol > 0.0 && max_iter >= 1 && degree >= 1, OVL_E_ARG, "bad eigensolver parameter");
     const int want = ell + std::max(8, ell / 10);  // cushion: a +-lambda pair may straddle the cut
     OVL_REQUIRE(ell >= 1 && m >= want, OVL_E_ARG, "need m >= ell + max(8, ell/10) vectors in V");
+    OVL_REQUIRE(want + 40 <= 512, OVL_E_ARG, "at most 429 eigenpairs (the Lanczos basis holds 512 vectors)");
     // Lanczos basis: 2 want (at least want + 40, at most 512) vectors, cut
     // back toward want + 40 while the basis and its work vectors would take
     // more than 90% of the free device memory (large volumes with many modes)

@@ -350,3 +350,18 @@ def test_sign_dslash_count_is_2n_plus_1(c1):
     launches, vectors = ctypes.c_int64(), ctypes.c_int64()
     ovl.ovl_counters(ctypes.byref(launches), ctypes.byref(vectors), 0)
     assert vectors.value == 2 * 37 + 1
+
+
+def test_eigs_rejects_more_than_429_pairs(c1):
+    """430 wanted pairs would not leave the thick restart room in the
+    512-vector Lanczos basis: refused before any device work (V is sized
+    correctly all the same)."""
+    g = ovl.Geometry(c1["dims"])
+    gauge = gu.make_gauge(g, c1["U"])
+    ell = 430
+    m = ell + ell // 10
+    V = gu.empty_field(g, ovl.OVL_F64, m)
+    lam = np.zeros(ell)
+    st = ovl.EigStats()
+    with pytest.raises(ovl.OvlError, match="429"):
+        ovl.ovl_hw_eigs(gauge, RHO, ell, m, V, lam, c1["hi"] * 1.01, 1e-10, 1, 10, ctypes.byref(st), None)
