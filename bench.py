@@ -433,8 +433,12 @@ def main():
 
     dslash = {}
     gauge.set_repr(ovl.OVL_F64, 0)
-    for name, p, L, nrhs in [("f64_18_1rhs", ovl.OVL_F64, 18, 1), ("f32_12_1rhs", ovl.OVL_F32, 12, 1),
-                             ("f16_12_1rhs", prec, 12, 1), ("f16_12_12rhs", prec, 12, 12)]:
+    for p in (ovl.OVL_F32, ovl.OVL_F16, ovl.OVL_BF16):
+        gauge.set_repr(p, 1)
+    for name, p, L, nrhs in [("f64_18_1rhs", ovl.OVL_F64, 18, 1), ("f64_18_12rhs", ovl.OVL_F64, 18, 12),
+                             ("f32_12_1rhs", ovl.OVL_F32, 12, 1), ("f32_12_12rhs", ovl.OVL_F32, 12, 12),
+                             ("f16_12_1rhs", ovl.OVL_F16, 12, 1), ("f16_12_12rhs", ovl.OVL_F16, 12, 12),
+                             ("bf16_12_1rhs", ovl.OVL_BF16, 12, 1), ("bf16_12_12rhs", ovl.OVL_BF16, 12, 12)]:
         t = stencil_time(p, nrhs)
         gbs = model_bytes(p, L, nrhs) / t / 1e9
         dslash[name] = {"us": round(t * 1e6, 2), "model_GBps": round(gbs, 1),
