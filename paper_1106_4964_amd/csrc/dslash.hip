@@ -136,32 +136,50 @@ __device__ inline void colour_mul(const Cx<T> (*u)[3], const Cx<T> (*h)[3], Cx<T
                     : row3<false, CHAIN>(u[a][0], u[a][1], u[a][2], h[s]);
 }
 
-template <int P>
+// FMA chains (fewer instructions) everywhere except the FP16 kernels with
+// extra epilogue vectors, where the pairwise-summed form measured faster.
+// FP16 chains take their operands through opaque(): otherwise the compiler
+// folds the FP16->FP32 conversions into mixed-precision FMAs that keep the
+// FP16 inputs live across the chains (about 200 VGPRs).
+template <int P, int NV>
 constexpr bool chain_form() {
-  return P != OVL_F16;
+  return P != OVL_F16 || NV == 0;
 }
 
-template <int P, int R, int MU, int KR>
+template <int P, bool CH, int N>
+__device__ inline void opaque(Cx<float>* v) {
+  if constexpr (P == OVL_F16 && CH) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) asm("" : "+v"(v[i].re), "+v"(v[i].im));
+  }
+}
+template <int P, bool CH, int N>
+__device__ inline void opaque(Cx<double>*) {}
+
+template <int P, int R, int MU, int KR, bool CH>
 __device__ inline void hop_dir(const StencilArgs& A, const char* in, int p, int h, const int* nb,
                                Cx<typename Prec<P>::real> (*acc)[12]) {
   using real = typename Prec<P>::real;
-  constexpr bool CH = chain_form<P>();
   const int q = 1 - p;
   Cx<real> s[12], hs[2][3], w[2][3], u[3][3];
   // forward: U_mu(x) (1 - gamma_mu) in(x + mu), the link shared by the KR vectors
   LinkIO<P, R>::load(A.links, MU, p, h, A.g.Nh, u);
+  opaque<P, CH, 9>(&u[0][0]);
 #pragma unroll
   for (int k = 0; k < KR; ++k) {
     SpinorIO<P>::load(in + k * A.vstride, q, nb[MU], A.g.Nh, s);
+    opaque<P, CH, 12>(s);
     project<MU, -1>(s, hs);
     colour_mul<false, CH>(u, hs, w);
     accumulate<MU, -1>(acc[k], w);
   }
   // backward: U_mu(x - mu)^dag (1 + gamma_mu) in(x - mu)
   LinkIO<P, R>::load(A.links, MU, q, nb[MU + 4], A.g.Nh, u);
+  opaque<P, CH, 9>(&u[0][0]);
 #pragma unroll
   for (int k = 0; k < KR; ++k) {
     SpinorIO<P>::load(in + k * A.vstride, q, nb[MU + 4], A.g.Nh, s);
+    opaque<P, CH, 12>(s);
     project<MU, +1>(s, hs);
     colour_mul<true, CH>(u, hs, w);
     accumulate<MU, +1>(acc[k], w);
@@ -239,10 +257,10 @@ __global__ __launch_bounds__(RIN ? 512 : 256) void stencil_kernel(StencilArgs A)
   for (int k = 0; k < KR; ++k)
 #pragma unroll
     for (int c = 0; c < 12; ++c) acc[k][c] = {real(0), real(0)};
-  hop_dir<P, R, 0, KR>(A, in, p, h, nb, acc);
-  hop_dir<P, R, 1, KR>(A, in, p, h, nb, acc);
-  hop_dir<P, R, 2, KR>(A, in, p, h, nb, acc);
-  hop_dir<P, R, 3, KR>(A, in, p, h, nb, acc);
+  hop_dir<P, R, 0, KR, chain_form<P, NV>()>(A, in, p, h, nb, acc);
+  hop_dir<P, R, 1, KR, chain_form<P, NV>()>(A, in, p, h, nb, acc);
+  hop_dir<P, R, 2, KR, chain_form<P, NV>()>(A, in, p, h, nb, acc);
+  hop_dir<P, R, 3, KR, chain_form<P, NV>()>(A, in, p, h, nb, acc);
 
 #pragma unroll
   for (int k = 0; k < KR; ++k) epilogue<P, NV>(A, voff + k * A.vstride, p, h, acc[k]);
@@ -271,7 +289,7 @@ __device__ inline void pipe_consume(const SpinorRaw<P>& sr, const LinkRaw<P, R>&
                                     Cx<typename Prec<P>::real>* acc) {
   using real = typename Prec<P>::real;
   constexpr int MU = D / 2;
-  constexpr bool CH = chain_form<P>();
+  constexpr bool CH = P != OVL_F16;  // the pipelined kernels keep the pairwise form for FP16
   Cx<real> s[12], hs[2][3], w[2][3], u[3][3];
   spinor_unpack<P>(sr, s);
   link_unpack<P, R>(lr, u);
