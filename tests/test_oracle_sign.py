@@ -270,3 +270,80 @@ def test_dense_sign_4444_with_projection():
     got = sign.sign_apply(lat, U, psi, 1.5, s, V, lam).reshape(-1)
     want = dense.exact_sign(H) @ psi.reshape(-1)
     assert np.linalg.norm(got - want) <= 1.01 * delta * np.linalg.norm(psi) + 1e-12
+
+
+# -- eq. (8): the mass term of D(m), pinned without overlap_apply's own algebra --
+def _free_field_plane_waves(lat, seed):
+    rng = np.random.default_rng(seed)
+    u = rng.standard_normal((4, 3)) + 1j * rng.standard_normal((4, 3))
+    for k in [(0, 0, 0, 0), (1, 0, 1, 0), (2, 3, 1, 1), (3, 1, 0, 1)]:
+        p = [2 * np.pi * k[mu] / lat.dims[mu] for mu in range(4)]
+        ph = np.array([np.exp(1j * sum(p[mu] * c for mu, c in enumerate(lat.coords(i)))) for i in range(lat.N)])
+        M = -1.5 + sum(1 - np.cos(q) for q in p)
+        sp = [np.sin(q) for q in p]
+        om = math.sqrt(M * M + sum(x * x for x in sp))
+        Dp = np.eye(4) + (M * np.eye(4) + 1j * sum(dirac.GAMMA[mu] * sp[mu] for mu in range(4))) / om
+        yield k, ph[:, None, None] * u[None], Dp
+
+
+def _eq8_free_field_error(apply_dm, m, dagger):
+    """max over plane waves of ||D(m) psi - want|| / ||psi|| with
+    want = [rho D(p) + m (1 - D(p)/2)] psi (eq. 8), D(p) the closed form of
+    the massless overlap at U = 1 (D(p)^dag for the adjoint)."""
+    lat = Lattice((4, 4, 2, 2))
+    rho = 1.5
+    worst = 0.0
+    for _, psi, Dp in _free_field_plane_waves(lat, 5):
+        Dx = Dp.conj().T if dagger else Dp
+        want = np.matmul(rho * Dx + m * (np.eye(4) - 0.5 * Dx), psi)
+        got = apply_dm(lat, si.unit_gauge_field(lat.dims), psi, rho, m, dagger)
+        worst = max(worst, np.linalg.norm(got - want) / np.linalg.norm(psi))
+    return worst
+
+
+_FREE_SIGN = sign.make_sign(0.5, 6.5, 120)
+
+
+def _oracle_dm(lat, U, psi, rho, m, dagger):
+    return sign.overlap_apply(lat, U, psi, rho, m, _FREE_SIGN, dagger=dagger)
+
+
+@pytest.mark.parametrize("dagger", [False, True])
+@pytest.mark.parametrize("m", [0.01, 0.05, 0.3])
+def test_massive_overlap_free_field_closed_form(m, dagger):
+    """eq. (8) D(m) = rho D + m (1 - D/2) and its adjoint against the
+    momentum-space closed form of D at U = 1 (not through massless_overlap),
+    to the sign error (rho - m/2) delta."""
+    delta = sign.measure_delta(_FREE_SIGN.coeffs, _FREE_SIGN.eps)
+    assert _eq8_free_field_error(_oracle_dm, m, dagger) <= 2 * 1.5 * delta + 1e-12
+
+
+@pytest.mark.parametrize("dagger", [False, True])
+def test_eq8_pin_catches_swapped_mass_term(dagger):
+    """The pin above fails for D(-m), i.e. rho +- m/2 swapped: at p = 0 the
+    massless D vanishes, so the two differ by 2 m ||psi||."""
+    def swapped(lat, U, psi, rho, m, dag):
+        return sign.overlap_apply(lat, U, psi, rho, -m, _FREE_SIGN, dagger=dag)
+
+    delta = sign.measure_delta(_FREE_SIGN.coeffs, _FREE_SIGN.eps)
+    for m in (0.01, 0.05):
+        assert _eq8_free_field_error(swapped, m, dagger) > 1.9 * m
+        assert _eq8_free_field_error(swapped, m, dagger) > 1e3 * (2 * 1.5 * delta + 1e-12)
+
+
+@pytest.mark.parametrize("m", [0.01, 0.05, 0.3])
+def test_massive_overlap_is_rho_d_plus_mass_term(small, m):
+    """eq. (8) on an interacting 2^4 field: the dense D(m) and D(m)^dag built
+    column by column from overlap_apply equal rho D + m (1 - D/2) and its
+    conjugate transpose, with D the dense massless overlap (eq. 3) on the
+    same polynomial."""
+    lat, U, H, lo, hi = small
+    rho = 1.5
+    s = sign.make_sign(lo, hi, 30)
+    D = dense.dense_operator(lat, lambda v: sign.massless_overlap(lat, U, v, rho, s))
+    Dm = dense.dense_operator(lat, lambda v: sign.overlap_apply(lat, U, v, rho, m, s))
+    Dmd = dense.dense_operator(lat, lambda v: sign.overlap_apply(lat, U, v, rho, m, s, dagger=True))
+    one = np.eye(D.shape[0])
+    want = rho * D + m * (one - 0.5 * D)
+    assert np.max(np.abs(Dm - want)) < 1e-12 * np.max(np.abs(want))
+    assert np.max(np.abs(Dmd - want.conj().T)) < 1e-12 * np.max(np.abs(want))
