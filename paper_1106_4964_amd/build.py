@@ -36,7 +36,7 @@ CXXFLAGS = [
     "-I" + INCLUDE,
     "-I" + CSRC,
 ]
-LDFLAGS = ["-shared", "--offload-arch=" + ARCH, "-lrocblas"]
+LDFLAGS = ["-shared", "--offload-arch=" + ARCH]
 
 
 def _sources():

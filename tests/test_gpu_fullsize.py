@@ -20,6 +20,11 @@ import gpu_util as gu  # noqa: E402
 F16, F64 = ovl.OVL_F16, ovl.OVL_F64
 U16 = gu.UNIT_ROUNDOFF[F16]
 RHO = 1.5
+# Element-wise bounds (max over the 12 vectors of max|got - want| / max|want|)
+# for F16 storage with FP32 arithmetic, about 2.5x the largest error measured
+# on MI355X: H_w 6.3e-4, sign application (n = 4) 9.5e-4.
+BOUND_HW_ELEMENTWISE = 1.5e-3
+BOUND_SIGN_ELEMENTWISE = 2.5e-3
 
 
 def _field(dims, seed=3):
@@ -36,6 +41,8 @@ def big():
 
 
 def test_hw_24x24x24x64_f16_12rhs(big):
+    """H_w on 12 F16 vectors in the tuned shape, every vector compared with
+    the oracle site by site (max |got - want| / max |want|)."""
     lat, U, g, gauge = big
     dims = lat.dims
     psi = np.stack([si.gaussian_spinor(dims, 800 + r) for r in range(12)])
@@ -45,17 +52,19 @@ def test_hw_24x24x24x64_f16_12rhs(big):
     ovl.ovl_hw_apply(y, x, gauge, RHO, F16, 12, None)
     shape = ovl.stencil_shape(g, F16, 1, 0, 12)
     got = gu.unpack(g, y, F16, 12)
-    for r in (0, 11):
-        want = dirac.hw_apply(lat, U, psi[r], RHO)
-        err = gu.rel_err(got[r], want)
-        print("H_w 24^3x64 F16, rhs %d, shape %s: rel err %.2e" % (r, shape, err))
-        assert err < 16 * U16 + 4e-7
+    errs = []
+    for r in range(12):
+        errs.append(gu.max_rel_err(got[r], dirac.hw_apply(lat, U, psi[r], RHO)))
+    print("H_w 24^3x64 F16, 12 rhs, shape %s: element-wise errors %s" % (shape, " ".join("%.2e" % e for e in errs)))
+    assert max(errs) < BOUND_HW_ELEMENTWISE
 
 
 def test_clenshaw_steps_24x24x24x64_f16_12rhs(big):
     """A sign application (n = 4) on the 12-rhs batch runs the Clenshaw-step
-    stencils with 0 and 3 extra epilogue vectors at full size; one vector is
-    compared with the oracle's recurrence on the same coefficients."""
+    stencils with 0 and 3 extra epilogue vectors at full size.  The inputs
+    are psi_a + c_r psi_b (c_r = r - 5.5), so the oracle's recurrence on
+    psi_a and psi_b gives all twelve expected outputs by linearity; each is
+    compared site by site."""
     lat, U, g, gauge = big
     dims = lat.dims
     v0 = gu.pack(g, si.gaussian_spinor(dims, 17), F64)
@@ -64,8 +73,11 @@ def test_clenshaw_steps_24x24x24x64_f16_12rhs(big):
     lam_max = lam.value * 1.01
     s = ovl.Sign(0.2 * lam_max, lam_max, n=4)
     so = sign.SignApprox(lam_max=lam_max, eps=s.eps, coeffs=s.coeffs())
-    psi = np.stack([si.gaussian_spinor(dims, 820 + r) for r in range(12)])
+    pa, pb = si.gaussian_spinor(dims, 820), si.gaussian_spinor(dims, 821)
+    coef = np.arange(12) - 5.5
+    psi = pa[None] + coef[:, None, None, None] * pb[None]
     x = gu.pack(g, psi, F16, 12)
+    del psi
     y = gu.empty_field(g, F16, 12)
     ovl.ovl_sign_apply(y, x, gauge, RHO, s, None, F16, 12, None)  # tunes the shapes
     ovl.ovl_stencil_timer(1)
@@ -75,11 +87,12 @@ def test_clenshaw_steps_24x24x24x64_f16_12rhs(big):
     n3, ms3 = ovl.stencil_timer_read(F16, 1, 3, 12)
     assert n3 >= 2
     got = gu.unpack(g, y, F16, 12)
-    want = sign.sign_apply(lat, U, psi[5], RHO, so)
-    err = gu.rel_err(got[5], want)
-    print("sign (n=4) 24^3x64 F16 12 rhs: rel err %.2e, 3-vector stencil %d launches, %.1f us, shape %s"
-          % (err, n3, 1e3 * ms3 / n3, ovl.stencil_shape(g, F16, 1, 3, 12)))
-    assert err < 1e-2
+    wa = sign.sign_apply(lat, U, pa, RHO, so)
+    wb = sign.sign_apply(lat, U, pb, RHO, so)
+    errs = [gu.max_rel_err(got[r], wa + coef[r] * wb) for r in range(12)]
+    print("sign (n=4) 24^3x64 F16 12 rhs: element-wise errors %s; 3-vector stencil %d launches, %.1f us, shape %s"
+          % (" ".join("%.2e" % e for e in errs), n3, 1e3 * ms3 / n3, ovl.stencil_shape(g, F16, 1, 3, 12)))
+    assert max(errs) < BOUND_SIGN_ELEMENTWISE
 
 
 def test_hw_32x32x32x64_f16_12rhs():
