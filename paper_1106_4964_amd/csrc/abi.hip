@@ -86,6 +86,22 @@ void ws_put(void* p, hipStream_t s) {
   P.free_list.insert({{s, P.sizes[p]}, p});
 }
 
+void ws_retire_stream(hipStream_t from, hipStream_t to) {
+  if (from == to) return;
+  Pool& P = pool();
+  std::lock_guard<std::mutex> lk(P.mu);
+  std::vector<std::pair<size_t, void*>> moved;
+  for (auto it = P.free_list.begin(); it != P.free_list.end();) {
+    if (it->first.first == from) {
+      moved.emplace_back(it->first.second, it->second);
+      it = P.free_list.erase(it);
+    } else {
+      ++it;
+    }
+  }
+  for (const auto& m : moved) P.free_list.insert({{to, m.first}, m.second});
+}
+
 }  // namespace ovl
 
 using namespace ovl;

@@ -578,6 +578,13 @@ namespace ovl {
 // while earlier kernels that used it are still running.
 void* ws_get(size_t bytes, hipStream_t s);
 void ws_put(void* p, hipStream_t s);
+// Hands every free buffer keyed by stream `from` over to stream `to`.  Safe
+// when `to` is ordered after all work queued on `from` so far (an event
+// wait, or a synchronize of `from`).  The solvers run on private streams:
+// they adopt the caller's free buffers at the start and hand theirs back
+// at the end, so repeated solves reuse one set of buffers and none is left
+// under a dead stream handle.
+void ws_retire_stream(hipStream_t from, hipStream_t to);
 // Accounting of the device memory the library holds (workspace pool,
 // eigensolver buffers, packed links): +bytes on allocation, -bytes on free.
 void mem_track(int64_t delta);

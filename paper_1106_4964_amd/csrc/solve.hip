@@ -187,6 +187,9 @@ int cg_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, doub
   OVL_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
   OVL_HIP(hipEventRecord(ev, us));
   OVL_HIP(hipStreamWaitEvent(s, ev, 0));
+  // s now runs after everything queued on the caller's stream, so the free
+  // workspace kept for that stream can serve this solve
+  ws_retire_stream(us, s);
 
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
@@ -409,6 +412,7 @@ int cg_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, doub
     if (graph) (void)hipGraphDestroy(graph);
     (void)hipStreamSynchronize(s);
     (void)hipEventDestroy(ev);
+    ws_retire_stream(s, us);
     (void)hipStreamDestroy(s);
     throw;
   }
@@ -419,6 +423,7 @@ int cg_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, doub
   OVL_HIP(hipStreamWaitEvent(us, ev, 0));
   OVL_HIP(hipStreamSynchronize(s));
   OVL_HIP(hipEventDestroy(ev));
+  ws_retire_stream(s, us);
   OVL_HIP(hipStreamDestroy(s));
   st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
   return rc;
@@ -455,6 +460,9 @@ int fgcr_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, do
   OVL_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
   OVL_HIP(hipEventRecord(ev, us));
   OVL_HIP(hipStreamWaitEvent(s, ev, 0));
+  // s now runs after everything queued on the caller's stream, so the free
+  // workspace kept for that stream can serve this solve
+  ws_retire_stream(us, s);
   int rc = OVL_OK;
   bool fallback = false;
   try {
@@ -640,6 +648,7 @@ int fgcr_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, do
   } catch (...) {
     (void)hipStreamSynchronize(s);
     (void)hipEventDestroy(ev);
+    ws_retire_stream(s, us);
     (void)hipStreamDestroy(s);
     throw;
   }
@@ -647,6 +656,7 @@ int fgcr_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, do
   OVL_HIP(hipStreamWaitEvent(us, ev, 0));
   OVL_HIP(hipStreamSynchronize(s));
   OVL_HIP(hipEventDestroy(ev));
+  ws_retire_stream(s, us);
   OVL_HIP(hipStreamDestroy(s));
   if (fallback) {
     // plain CG finishes the solve from the current x
@@ -712,6 +722,9 @@ int cg_multimass(void* const* xs, const void* b, int R, const ovl_gauge* u, doub
   OVL_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
   OVL_HIP(hipEventRecord(ev, us));
   OVL_HIP(hipStreamWaitEvent(s, ev, 0));
+  // s now runs after everything queued on the caller's stream, so the free
+  // workspace kept for that stream can serve this solve
+  ws_retire_stream(us, s);
   int its = 0;
   try {
     WsBuf r64(v64 * R, s), q64(v64 * R, s), t64(v64 * R, s), pP(vP * R, s), qP(vP * R, s), tP(vP * R, s);
@@ -866,6 +879,7 @@ int cg_multimass(void* const* xs, const void* b, int R, const ovl_gauge* u, doub
   } catch (...) {
     (void)hipStreamSynchronize(s);
     (void)hipEventDestroy(ev);
+    ws_retire_stream(s, us);
     (void)hipStreamDestroy(s);
     throw;
   }
@@ -873,6 +887,7 @@ int cg_multimass(void* const* xs, const void* b, int R, const ovl_gauge* u, doub
   OVL_HIP(hipStreamWaitEvent(us, ev, 0));
   OVL_HIP(hipStreamSynchronize(s));
   OVL_HIP(hipEventDestroy(ev));
+  ws_retire_stream(s, us);
   OVL_HIP(hipStreamDestroy(s));
   const double t_shift = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
   if (log_on()) fprintf(stderr, "[ovl multimass] shifted CG: %d iterations, %.2f s\n", its, t_shift);

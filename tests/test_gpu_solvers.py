@@ -365,3 +365,39 @@ def test_eigs_rejects_more_than_429_pairs(c1):
     st = ovl.EigStats()
     with pytest.raises(ovl.OvlError, match="429"):
         ovl.ovl_hw_eigs(gauge, RHO, ell, m, V, lam, c1["hi"] * 1.01, 1e-10, 1, 10, ctypes.byref(st), None)
+
+
+def test_repeated_solves_keep_device_memory_flat(c1):
+    """The solvers run on private streams; the workspace they release must be
+    reusable by the next solve, so the library's device memory stays flat
+    after the first of several identical solves (CG with graphs, FGCR and
+    multi-mass CG each called repeatedly)."""
+    g = ovl.Geometry(c1["dims"])
+    gauge = gu.make_gauge(g, c1["U"], [(ovl.OVL_F32, 1), (ovl.OVL_F32, 0)])
+    s = ovl.Sign(c1["lo"], c1["hi"] * 1.0001, n=60)
+    R = 3
+    b = gu.pack(g, si.point_sources(c1["dims"])[:R], ovl.OVL_F64, R)
+    live = ctypes.c_int64()
+    history = []
+    for call in range(5):
+        x = torch.zeros(g.spinor_bytes(ovl.OVL_F64, R), dtype=torch.uint8, device=gu.DEV)
+        st = ovl.SolveStats()
+        rc = ovl.ovl_cg_solve(x, b, R, gauge, RHO, 0.05, s, None, 1e-10, 5000,
+                              ovl.SolveOpts(ovl.OVL_F32, 1e-3, 4, 1, 60), ctypes.byref(st), None)
+        assert rc == 0
+        x2 = torch.zeros_like(x)
+        st2 = ovl.SolveStats()
+        rc = ovl.ovl_fgcr_solve(x2, b, R, gauge, RHO, 0.05, s, None, None, 8, 1e-10, 5000,
+                                ovl.SolveOpts(ovl.OVL_F32, 1e-3, 0, 1, 60), ctypes.byref(st2), None)
+        assert rc == 0
+        xs = [torch.zeros_like(x) for _ in range(2)]
+        ptrs = (ctypes.c_void_p * 2)(*[t.data_ptr() for t in xs])
+        sts = (ovl.SolveStats * 2)()
+        rc = ovl.ovl_cg_multimass(ptrs, b, R, gauge, RHO, np.array([0.05, 0.1]), 2, s, None, 1e-10, 5000,
+                                  ovl.SolveOpts(ovl.OVL_F32, 1e-3, 0, 1, 60), sts, None)
+        assert rc == 0
+        torch.cuda.synchronize()
+        ovl.ovl_mem_stats(ctypes.byref(live), None, 0)
+        history.append(live.value)
+    print("library device memory after each round of solves:", history)
+    assert all(h == history[0] for h in history[1:]), history
