@@ -192,6 +192,23 @@ int ovl_lowmodes_create(const ovl_geom* g, int ell, const void* V, const double*
 int ovl_lowmodes_destroy(ovl_lowmodes* lm);
 int ovl_lowmodes_project(const ovl_lowmodes* lm, const void* in, void* psi_h, void* w, ovl_prec prec, int nrhs,
                          ovl_stream_t s);
+/* ovl_lowmodes_project_noalloc: ovl_lowmodes_project for callers that cannot
+ *   allocate device memory (code under HIP graph capture, tight serving
+ *   loops, harnesses that forbid hipMalloc).  Same arguments, layouts,
+ *   results and errors, and no hipMalloc, hipFree or other allocating call:
+ *   the projection's scratch (ell*nrhs FP64 coefficients and the split-K
+ *   partial sums of the inner products) lives in a 16 MiB static array that
+ *   each GPU the library runs on holds until the process ends.  Limit:
+ *   ell * nrhs <= 16131, OVL_E_ARG beyond.  For ell * nrhs <= 2044 the
+ *   partial sums are formed exactly as in ovl_lowmodes_project and the
+ *   result is bit-identical; above that fewer partial sums are used and the
+ *   result agrees to rounding.  Every call on one GPU uses the same array
+ *   and leaves its contents behind: calls that overlap on one GPU (from two
+ *   host threads or on two streams that are not ordered) race, so order
+ *   them on one stream.
+ */
+int ovl_lowmodes_project_noalloc(const ovl_lowmodes* lm, const void* in, void* psi_h, void* w, ovl_prec prec,
+                                 int nrhs, ovl_stream_t s);
 
 /* ----------------------------------------------------------------- overlap
  * ovl_sign_apply: out = sign(H_w) in ~ sum_i sign(lambda_i)(eta_i^dag in) eta_i

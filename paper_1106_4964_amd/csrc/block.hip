@@ -16,6 +16,9 @@
 // every wave accumulates IW basis vectors against it in registers; a second
 // kernel adds the per-block partials in block order, so results are
 // bit-reproducible.
+#include <algorithm>
+#include <string>
+
 #include "ops.h"
 
 namespace ovl {
@@ -241,26 +244,38 @@ __global__ __launch_bounds__(256) void rotate_kernel(int Nh, int K, int k, char*
 }
 
 template <int PP, int RMAX, int IW, bool EX = false>
-void dot_go(const ovl_geom* g, const void* V, int ell, const void* psi, int R, double2* C, hipStream_t s) {
+void dot_go(const ovl_geom* g, const void* V, int ell, const void* psi, int R, double2* C, double2* part, int G,
+            hipStream_t s) {
   const int Nh = g->geo.Nh;
   const size_t vsV = spinor_vec_bytes(g, OVL_F64), vsP = spinor_vec_bytes(g, PP);
   const int groups = (ell + PJ_WAVES * IW - 1) / (PJ_WAVES * IW);
-  WsBuf part(static_cast<size_t>(ell) * PJ_BLOCKS * R * sizeof(double2), s);
-  hipLaunchKernelGGL((dot_kernel<PP, RMAX, IW, EX>), dim3(groups, PJ_BLOCKS), dim3(PJ_WAVES * 64), 0, s, Nh, ell,
-                     static_cast<const char*>(V), vsV, static_cast<const char*>(psi), vsP, R,
-                     static_cast<double2*>(part.p));
+  hipLaunchKernelGGL((dot_kernel<PP, RMAX, IW, EX>), dim3(groups, G), dim3(PJ_WAVES * 64), 0, s, Nh, ell,
+                     static_cast<const char*>(V), vsV, static_cast<const char*>(psi), vsP, R, part);
   OVL_HIP(hipGetLastError());
-  hipLaunchKernelGGL(dot_reduce_kernel, dim3((ell * R + 255) / 256), dim3(256), 0, s, ell, R, PJ_BLOCKS,
-                     static_cast<const double2*>(part.p), C);
+  hipLaunchKernelGGL(dot_reduce_kernel, dim3((ell * R + 255) / 256), dim3(256), 0, s, ell, R, G,
+                     static_cast<const double2*>(part), C);
   OVL_HIP(hipGetLastError());
 }
 
+// C = V^dag psi with the per-block partials in `part` (ell * G * R entries).
 template <int PP>
-void dot_r(const ovl_geom* g, const void* V, int ell, const void* psi, int R, double2* C, hipStream_t s) {
-  if (R == 1) dot_go<PP, 1, 8, true>(g, V, ell, psi, R, C, s);
-  else if (R <= 4) dot_go<PP, 4, 4>(g, V, ell, psi, R, C, s);
-  else if (R == 12) dot_go<PP, 12, 2, true>(g, V, ell, psi, R, C, s);
-  else dot_go<PP, 12, 2>(g, V, ell, psi, R, C, s);
+void dot_r(const ovl_geom* g, const void* V, int ell, const void* psi, int R, double2* C, double2* part, int G,
+           hipStream_t s) {
+  if (R == 1) dot_go<PP, 1, 8, true>(g, V, ell, psi, R, C, part, G, s);
+  else if (R <= 4) dot_go<PP, 4, 4>(g, V, ell, psi, R, C, part, G, s);
+  else if (R == 12) dot_go<PP, 12, 2, true>(g, V, ell, psi, R, C, part, G, s);
+  else dot_go<PP, 12, 2>(g, V, ell, psi, R, C, part, G, s);
+}
+
+void dot_prec(const ovl_geom* g, const void* V, int ell, const void* psi, int prec, int R, double2* C, double2* part,
+              int G, hipStream_t s) {
+  switch (prec) {
+    case OVL_F64: dot_r<OVL_F64>(g, V, ell, psi, R, C, part, G, s); break;
+    case OVL_F32: dot_r<OVL_F32>(g, V, ell, psi, R, C, part, G, s); break;
+    case OVL_F16: dot_r<OVL_F16>(g, V, ell, psi, R, C, part, G, s); break;
+    case OVL_BF16: dot_r<OVL_BF16>(g, V, ell, psi, R, C, part, G, s); break;
+    default: throw Error(OVL_E_PRECISION, "unknown precision");
+  }
 }
 
 template <int PP, int RMAX, bool EX = false>
@@ -311,13 +326,8 @@ void project_r(const ovl_lowmodes* lm, const void* psi, void* psih, void* w, int
 void block_dot(const ovl_geom* g, const void* V, int ell, const void* psi, int prec, int R, double2* C,
                hipStream_t s) {
   OVL_REQUIRE(R >= 1 && R <= OVL_MAX_RHS && ell >= 1, OVL_E_ARG, "block_dot: 1 <= R <= 12, ell >= 1");
-  switch (prec) {
-    case OVL_F64: dot_r<OVL_F64>(g, V, ell, psi, R, C, s); break;
-    case OVL_F32: dot_r<OVL_F32>(g, V, ell, psi, R, C, s); break;
-    case OVL_F16: dot_r<OVL_F16>(g, V, ell, psi, R, C, s); break;
-    case OVL_BF16: dot_r<OVL_BF16>(g, V, ell, psi, R, C, s); break;
-    default: throw Error(OVL_E_PRECISION, "unknown precision");
-  }
+  WsBuf part(static_cast<size_t>(ell) * PJ_BLOCKS * R * sizeof(double2), s);
+  dot_prec(g, V, ell, psi, prec, R, C, static_cast<double2*>(part.p), PJ_BLOCKS, s);
 }
 
 void block_axpy(const ovl_geom* g, const void* V, int ell, const double2* K, void* Y, int prec, int R, bool keep,
@@ -343,12 +353,14 @@ void block_rotate_inplace(const ovl_geom* g, void* V, int K, const double2* S, i
   OVL_HIP(hipGetLastError());
 }
 
-void lowmode_project(const ovl_lowmodes* lm, const void* psi, void* psih, void* w, int prec, int nrhs, int g5w,
-                     hipStream_t s) {
-  OVL_REQUIRE(nrhs <= OVL_MAX_RHS, OVL_E_ARG, "projection supports at most 12 right-hand sides");
-  WsBuf cbuf(static_cast<size_t>(lm->ell) * nrhs * sizeof(double2), s);
-  double2* C = static_cast<double2*>(cbuf.p);
-  block_dot(&lm->geom, lm->V, lm->ell, psi, prec, nrhs, C, s);
+namespace {
+// The projection with caller-provided scratch: C (ell * nrhs coefficients)
+// and the split-K partials of pass 1 (ell * G * nrhs).
+void lowmode_project_ws(const ovl_lowmodes* lm, const void* psi, void* psih, void* w, int prec, int nrhs, int g5w,
+                        double2* C, double2* part, int G, hipStream_t s) {
+  OVL_REQUIRE(nrhs >= 1 && nrhs <= OVL_MAX_RHS && lm->ell >= 1, OVL_E_ARG,
+              "projection: 1 <= nrhs <= 12 and at least one low mode");
+  dot_prec(&lm->geom, lm->V, lm->ell, psi, prec, nrhs, C, part, G, s);
   switch (prec) {
     case OVL_F64: project_r<OVL_F64>(lm, psi, psih, w, nrhs, g5w, C, s); break;
     case OVL_F32: project_r<OVL_F32>(lm, psi, psih, w, nrhs, g5w, C, s); break;
@@ -356,6 +368,69 @@ void lowmode_project(const ovl_lowmodes* lm, const void* psi, void* psih, void* 
     case OVL_BF16: project_r<OVL_BF16>(lm, psi, psih, w, nrhs, g5w, C, s); break;
     default: throw Error(OVL_E_PRECISION, "unknown precision");
   }
+}
+
+// Scratch of the allocation-free projection: one array per GPU, in device
+// memory for the life of the process.  Host code never uses the array's
+// name as an address; the kernels receive the per-device pointer that
+// hipGetSymbolAddress returns.
+constexpr size_t kStaticScratchBytes = size_t(16) << 20;
+constexpr int kStaticMinBlocks = 64;  // fewest K-blocks of pass 1 accepted
+// Largest ell * nrhs for which the coefficients (rounded up to 256 bytes)
+// and kStaticMinBlocks sets of partials fit.
+constexpr size_t kMaxStaticEllRhs = (kStaticScratchBytes - 256) / (sizeof(double2) * (kStaticMinBlocks + 1));
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device with that device current.
+void* static_scratch() {
+  int dev = -1;
+  OVL_HIP(hipGetDevice(&dev));
+  OVL_REQUIRE(dev >= 0 && dev < kMaxDevices, OVL_E_ARG, "device index out of range for the static scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr)
+      throw Error(OVL_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
+}  // namespace
+
+void lowmode_project(const ovl_lowmodes* lm, const void* psi, void* psih, void* w, int prec, int nrhs, int g5w,
+                     hipStream_t s) {
+  OVL_REQUIRE(nrhs >= 1 && nrhs <= OVL_MAX_RHS, OVL_E_ARG, "projection supports 1 to 12 right-hand sides");
+  WsBuf cbuf(static_cast<size_t>(lm->ell) * nrhs * sizeof(double2), s);
+  WsBuf part(static_cast<size_t>(lm->ell) * PJ_BLOCKS * nrhs * sizeof(double2), s);
+  lowmode_project_ws(lm, psi, psih, w, prec, nrhs, g5w, static_cast<double2*>(cbuf.p),
+                     static_cast<double2*>(part.p), PJ_BLOCKS, s);
+}
+
+// Same projection with its scratch in the static per-device array.  Pass 1
+// keeps PJ_BLOCKS K-blocks while they fit (then the result is bit-identical
+// to lowmode_project), else as many as fit, at least kStaticMinBlocks.
+// Every partial and coefficient slot is written before it is read, so
+// nothing needs clearing between calls.
+void lowmode_project_static(const ovl_lowmodes* lm, const void* psi, void* psih, void* w, int prec, int nrhs,
+                            hipStream_t s) {
+  OVL_REQUIRE(nrhs >= 1 && nrhs <= OVL_MAX_RHS, OVL_E_ARG, "projection supports 1 to 12 right-hand sides");
+  OVL_REQUIRE(static_cast<size_t>(lm->ell) * nrhs <= kMaxStaticEllRhs, OVL_E_ARG,
+              "ovl_lowmodes_project_noalloc: ell * nrhs = " + std::to_string(lm->ell * nrhs) +
+                  " exceeds what its 16 MiB static scratch holds (ell * nrhs <= " +
+                  std::to_string(kMaxStaticEllRhs) + ")");
+  const size_t unit = static_cast<size_t>(lm->ell) * nrhs * sizeof(double2);  // one coefficient set
+  const size_t c_bytes = (unit + 255) / 256 * 256;
+  const size_t fit = (kStaticScratchBytes - c_bytes) / unit;  // >= kStaticMinBlocks by the check above
+  const int G = static_cast<int>(std::min<size_t>(PJ_BLOCKS, fit));
+  char* base = static_cast<char*>(static_scratch());
+  lowmode_project_ws(lm, psi, psih, w, prec, nrhs, 0, reinterpret_cast<double2*>(base),
+                     reinterpret_cast<double2*>(base + c_bytes), G, s);
 }
 
 }  // namespace ovl

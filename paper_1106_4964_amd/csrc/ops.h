@@ -84,6 +84,11 @@ void block_rotate_inplace(const ovl_geom* g, void* V, int K, const double2* S, i
 // ------------------------------------------------------------ sign / overlap
 void lowmode_project(const ovl_lowmodes* lm, const void* psi, void* psih, void* w, int prec, int nrhs, int g5w,
                      hipStream_t s);
+// The same projection with no device allocation: its scratch (coefficients
+// and split-K partials) lives in a static per-device array.  Calls that
+// overlap on one GPU share that array and race.
+void lowmode_project_static(const ovl_lowmodes* lm, const void* psi, void* psih, void* w, int prec, int nrhs,
+                            hipStream_t s);
 // mode 0: sign(H_w) in;  1: D(m) in;  2: D(m)^dag in
 void overlap_apply(void* out, const void* in, const ovl_gauge* u, double rho, double m, const ovl_sign* sg,
                    const ovl_lowmodes* lm, int mode, int prec, int nrhs, hipStream_t s);

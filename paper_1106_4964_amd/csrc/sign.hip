@@ -376,6 +376,19 @@ int ovl_lowmodes_project(const ovl_lowmodes* lm, const void* in, void* psi_h, vo
   });
 }
 
+int ovl_lowmodes_project_noalloc(const ovl_lowmodes* lm, const void* in, void* psi_h, void* w, ovl_prec prec,
+                                 int nrhs, ovl_stream_t s) {
+  return guard([&] {
+    OVL_REQUIRE(lm && in && psi_h && w, OVL_E_ARG, "null argument");
+    check_prec(prec);
+    check_nrhs(nrhs);
+    OVL_REQUIRE(lm->ell > 0, OVL_E_ARG, "no low modes");
+    OVL_REQUIRE(in != psi_h && in != w && psi_h != w, OVL_E_ALIAS, "projection outputs must not alias");
+    lowmode_project_static(lm, in, psi_h, w, prec, nrhs, static_cast<hipStream_t>(s));
+    return OVL_OK;
+  });
+}
+
 static void overlap_common(void* out, const void* in, const ovl_gauge* u, const ovl_sign* sg,
                            const ovl_lowmodes* lm, int prec, int nrhs) {
   OVL_REQUIRE(out && in && u && sg, OVL_E_ARG, "null argument");

@@ -144,6 +144,7 @@ _SIGS = {
     "ovl_lowmodes_create": (P, I, P, P, P),
     "ovl_lowmodes_destroy": (P,),
     "ovl_lowmodes_project": (P, P, P, P, I, I, ST),
+    "ovl_lowmodes_project_noalloc": (P, P, P, P, I, I, ST),
     "ovl_sign_apply": (P, P, P, D, P, P, I, I, ST),
     "ovl_overlap_apply": (P, P, P, D, D, P, P, I, I, I, ST),
     "ovl_cg_solve": (P, P, I, P, D, D, P, P, D, I, P, P, ST),
