@@ -42,8 +42,10 @@ HBM_PEAK_GBS = 8000.0
 # stencil configuration: (extra epilogue vectors, tuned shape kr, bs, pipe,
 # rin, tm).  Summary and commands: profiles/stencil_f16_12rhs_24x24x24x64_counters.md
 PROFILED_TRAFFIC = {
-    (3, (2, 128, 0, 0, 0)): 4041877504,
-    (0, (2, 128, 0, 0, 0)): 2987828224,
+    (3, (2, 128, 0, 0, 0)): 4080216064,
+    (0, (2, 128, 0, 0, 0)): 3094016000,
+    (3, (2, 256, 0, 0, 0)): 4072608000,
+    (0, (2, 256, 0, 0, 0)): 3037061120,
 }
 
 
@@ -61,13 +63,13 @@ def parse():
     ap.add_argument("--delta", type=float, default=1e-10)
     ap.add_argument("--prec", type=str, default="f16")
     ap.add_argument("--no-cg", action="store_true")
-    ap.add_argument("--cg-masses", type=str, default="0.01")
+    ap.add_argument("--cg-masses", type=str, default="0.01,0.05")
     ap.add_argument("--inner-delta", type=float, default=1e-3,
                     help="sign accuracy of the inner (low-precision) operator; 0 = same as outer")
     ap.add_argument("--inner-tol", type=float, default=1e-3)
     ap.add_argument("--graph-chunk", type=int, default=8)
     ap.add_argument("--fp64-cg-rhs", type=int, default=1,
-                    help="rhs of the plain FP64 CG comparison (time scaled to 12); 0 = skip")
+                    help="rhs of the full plain FP64 CG solve (its iteration count and time, scaled to 12); 0 = skip")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--mode", choices=["full", "kernels", "learned"], default="full",
                     help="kernels: only a 1 GiB calibration copy and the stencil configurations "
@@ -76,13 +78,23 @@ def parse():
     ap.add_argument("--pairs", type=int, default=2000, help="learned mode: training pairs (four fields)")
     ap.add_argument("--restart", type=int, default=16, help="learned mode: FGCR restart length")
     ap.add_argument("--cpu-only", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-data", type=str, default="", help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-seed", type=int, default=0, help=argparse.SUPPRESS)
+    ap.add_argument("--no-c2", action="store_true", help="skip the 16^3x32 block (C2)")
+    ap.add_argument("--shape", type=str, default="",
+                    help="kernels mode: pin the 12-rhs stencil shape kr,bs,pipe,rin,tm for the sign applications")
+    ap.add_argument("--fp64-batched-iters", type=int, default=12,
+                    help="inner iterations timed for the batched 12-rhs plain FP64 CG (0 = skip)")
     return ap.parse_args()
 
 
 # ---------------------------------------------------------------------------
 # CPU baseline: the oracle, timed in a child process limited to one thread
 # ---------------------------------------------------------------------------
-def cpu_baseline_child(dims, n, ell):
+def cpu_baseline_child(dims, n, ell, data_dir, seed):
+    """One single-threaded oracle process: 3 H_w applications and the
+    projection on 4 vectors, on the links in data_dir (written once by the
+    parent) and a spinor of its own seed."""
     import numpy as np
 
     import synth_inputs as si
@@ -90,8 +102,9 @@ def cpu_baseline_child(dims, n, ell):
     from oracle.lattice import Lattice
 
     lat = Lattice(dims)
-    U = si.gauge_field(dims, 0.25, 3)
-    psi = si.gaussian_spinor(dims, 103)
+    U = np.load(os.path.join(data_dir, "links.npy"), mmap_mode="r")
+    U = np.ascontiguousarray(U)
+    psi = si.gaussian_spinor(dims, 103 + seed)
     reps = 3
     t0 = time.perf_counter()
     for _ in range(reps):
@@ -106,31 +119,68 @@ def cpu_baseline_child(dims, n, ell):
     print(json.dumps({"t_dw": t_dw, "t_proj4": t_proj4, "t_apply": t_apply, "reps": reps}))
 
 
-def cpu_baseline(dims, n, ell):
+def _cpu_children(dims, n, ell, data_dir, nproc):
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
     env["HIP_VISIBLE_DEVICES"] = ""
-    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-only", "--dims", ",".join(map(str, dims)),
-           "--ell", str(ell), "--delta", str(n)]
-    r = subprocess.run(cmd, capture_output=True, text=True, env=env, timeout=600)
-    if r.returncode != 0:
-        raise RuntimeError("cpu baseline failed: " + r.stderr[-2000:])
-    d = json.loads(r.stdout.strip().splitlines()[-1])
+    procs = []
+    for k in range(nproc):
+        cmd = [sys.executable, os.path.abspath(__file__), "--cpu-only", "--dims", ",".join(map(str, dims)),
+               "--ell", str(ell), "--delta", str(n), "--cpu-data", data_dir, "--cpu-seed", str(k)]
+        procs.append(subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, env=env))
+    out = []
+    for pr in procs:
+        so, se = pr.communicate(timeout=900)
+        if pr.returncode != 0:
+            raise RuntimeError("cpu baseline child failed: " + se[-2000:])
+        out.append(json.loads(so.strip().splitlines()[-1]))
+    return out
+
+
+def cpu_model():
+    try:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=30).stdout
+        for line in txt.splitlines():
+            if line.startswith("Model name"):
+                return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(dims, n, ell, data_dir):
+    """The oracle on this host: one process alone (1 thread), then one
+    single-threaded process per core of the job's CPU share at once (numpy's
+    stencil is single-threaded, so processes are how it uses every core).
+    Throughput = sum over processes of 1 / (time of one extrapolated apply)."""
+    nproc_host = os.cpu_count() or 1
+    share = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    cores = max(1, min(nproc_host, share if share > 0 else nproc_host, 16))
+    one = _cpu_children(dims, n, ell, data_dir, 1)[0]
+    many = _cpu_children(dims, n, ell, data_dir, cores) if cores > 1 else [one]
+    v1 = 1.0 / one["t_apply"]
+    vall = sum(1.0 / d["t_apply"] for d in many)
+    t_dw_all = sum(d["t_dw"] for d in many) / len(many)
     return {
-        "value": 1.0 / d["t_apply"],
+        "value": vall,
         "unit": "D_ov applies/s",
-        "cores": 1,
+        "cores": cores,
         "kind": "oracle",
-        "sample": ("FP64 numpy oracle, one thread: %d H_w applications at %s (%.2f s each) and the "
-                   "projection on 4 vectors (%.2f s), extrapolated to one overlap apply of 2n+1 = %d "
-                   "stencil applications and %d projected vectors"
-                   % (d["reps"], "x".join(map(str, dims)), d["t_dw"], d["t_proj4"], 2 * n + 1, ell)),
+        "sample": ("FP64 numpy oracle, %d single-threaded processes at once (one per core): each times 3 H_w "
+                   "applications at %s (%.2f s each on average) and the projection on 4 vectors, extrapolated to "
+                   "one overlap apply of 2n+1 = %d stencil applications and %d projected vectors; the same sample "
+                   "alone on one thread: %.5f applies/s (H_w %.2f s)"
+                   % (cores, "x".join(map(str, dims)), t_dw_all, 2 * n + 1, ell, v1, one["t_dw"])),
+        "one_thread_value": v1,
+        "nproc": nproc_host,
+        "cpu_model": cpu_model(),
+        "gflops_per_core_dslash": round(1368.0 * math.prod(dims) / one["t_dw"] / 1e9, 3),
     }
 
 
 # ---------------------------------------------------------------------------
 # Counter runs: a plain copy of known size, then each stencil configuration
 # ---------------------------------------------------------------------------
-def kernels_mode(dims, prec_name):
+def kernels_mode(dims, prec_name, shape=None):
     import numpy as np
     import torch
 
@@ -157,6 +207,9 @@ def kernels_mode(dims, prec_name):
     torch.cuda.synchronize()
     log("calibration copy: %d bytes read and written per launch" % (a.numel() * 4))
     del a, c
+    if shape:
+        for nv in range(4):
+            ovl.stencil_set_shape(g, prec, 1, nv, 12, shape)
     for name, p, nrhs in [("f16_12_12rhs", prec, 12), ("f16_12_1rhs", prec, 1),
                           ("f32_12_1rhs", ovl.OVL_F32, 1), ("f64_18_1rhs", ovl.OVL_F64, 1)]:
         x = torch.empty(g.spinor_bytes(p, nrhs), dtype=torch.uint8, device=dev)
@@ -169,7 +222,8 @@ def kernels_mode(dims, prec_name):
         torch.cuda.synchronize()
         log("stencil %s: shape (kr, bs, pipe, rin, tm) = %s" % (name, ovl.stencil_shape(g, p, p != ovl.OVL_F64, 0, nrhs)))
     # the Clenshaw recurrence of the sign function on 12 rhs: its steps are
-    # the stencil with 0 and with 3 extra epilogue vectors
+    # the stencil with 0 and with 3 extra epilogue vectors (in a pinned shape
+    # when one is given, else the tuned one)
     x = torch.empty(g.spinor_bytes(prec, 12), dtype=torch.uint8, device=dev)
     ovl.ovl_convert(g, b64, ovl.OVL_F64, x, prec, 12, None)
     y = torch.empty_like(x)
@@ -324,11 +378,99 @@ def learned_mode(args, dims):
 
 
 # ---------------------------------------------------------------------------
+def c2_block(ovl, args):
+    """16^3x32 (the second workload): 50 projected H_w modes, sign to 1e-10;
+    FP64 / FP32 / F16 storage: stencil GB/s and D(m) applies/s on one vector,
+    and CG at m = 0.01 on one point source to an FP64 true residual of 1e-10
+    (plain FP64, and mixed with an FP32 or F16 inner solve)."""
+    import torch
+
+    import synth_inputs as si
+
+    dev = torch.device("cuda:0")
+    dims, rho, m, ell = (16, 16, 16, 32), 1.5, 0.01, 50
+    g = ovl.Geometry(dims)
+    gauge = ovl.Gauge(g, torch.from_numpy(si.gauge_field(dims, 0.25, 2)).to(dev))
+    for p in (ovl.OVL_F32, ovl.OVL_F16):
+        gauge.set_repr(p, 1)
+    t0 = time.perf_counter()
+    lam_max, lams, V, lm, sgn = spectral_setup(ovl, g, gauge, dims, rho, ell, 1e-10, 2000)
+    t_setup = time.perf_counter() - t0
+    sgn_in = ovl.Sign(abs(lams[-1]), lam_max, delta=1e-3)
+    b64 = torch.empty(g.spinor_bytes(ovl.OVL_F64), dtype=torch.uint8, device=dev)
+    ovl.ovl_pack_spinor(g, torch.from_numpy(si.point_source(dims, 0, 0)[None]).to(dev), b64, ovl.OVL_F64, 1, None)
+    out = {"workload": "16x16x16x32, %d projected modes, sign delta 1e-10 (n=%d, sqrt(eps)=%.4f), m=%g, one point "
+                       "source" % (ell, sgn.n, math.sqrt(sgn.eps), m),
+           "setup_seconds": round(t_setup, 1)}
+    N = g.N
+    for name, p, L in [("f64", ovl.OVL_F64, 18), ("f32", ovl.OVL_F32, 12), ("f16", ovl.OVL_F16, 12)]:
+        x = torch.empty(g.spinor_bytes(p), dtype=torch.uint8, device=dev)
+        ovl.ovl_convert(g, b64, ovl.OVL_F64, x, p, 1, None)
+        y = torch.empty_like(x)
+        z = torch.empty_like(x)
+        bpr = {ovl.OVL_F64: 8, ovl.OVL_F32: 4, ovl.OVL_F16: 2}[p]
+        t_dw = _event_time(lambda: ovl.ovl_hw_apply(y, x, gauge, rho, p, 1, None), 20)
+        t_ov = _event_time(lambda: ovl.ovl_overlap_apply(z, x, gauge, rho, m, sgn, lm, 0, p, 1, None), 3)
+        rec = {"dslash_us": round(t_dw * 1e6, 2), "dslash_model_GBps": round(N * bpr * (4 * L + 48) / t_dw / 1e9, 1),
+               "overlap_applies_per_s": round(1.0 / t_ov, 2)}
+        xs = torch.zeros(g.spinor_bytes(ovl.OVL_F64), dtype=torch.uint8, device=dev)
+        if p == ovl.OVL_F64:
+            opts = ovl.SolveOpts(p, 0.0, 0, 1, 60)
+        else:
+            opts = ovl.SolveOpts(p, 1e-3, 8, 1, 60, None, None, 0, sgn_in.handle.value)
+        st = ovl.SolveStats()
+        rc = ovl.ovl_cg_solve(xs, b64, 1, gauge, rho, m, sgn, lm, 1e-10, 20000, opts, st, None)
+        rec["cg"] = {"rc": rc, "seconds": round(st.seconds, 3), "iterations": st.iterations, "restarts": st.restarts,
+                     "true_residual": st.true_residual[0], "sign_applies": st.sign_applies}
+        log("C2 %s: %s" % (name, rec))
+        out[name] = rec
+    out["cg_speedup_f16_vs_f64"] = round(out["f64"]["cg"]["seconds"] / out["f16"]["cg"]["seconds"], 2)
+    out["cg_speedup_f32_vs_f64"] = round(out["f64"]["cg"]["seconds"] / out["f32"]["cg"]["seconds"], 2)
+    del lm, V
+    return out
+
+
+def _event_time(fn, reps):
+    """Seconds per call of fn, timed with HIP events on torch's current stream
+    (the stream the library's kernels are launched on) after one warm-up."""
+    import torch
+
+    fn()
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        fn()
+    e1.record(s)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps * 1e-3
+
+
+def _event_time_cold(fn, reps, scratch):
+    """Median seconds of single calls of fn, each after writing a 1 GiB
+    scratch buffer (evicts L2 and the 256 MB MALL), timed with HIP events."""
+    import torch
+
+    fn()
+    s = torch.cuda.current_stream()
+    ts = []
+    for _ in range(reps):
+        scratch.fill_(1)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        fn()
+        e1.record(s)
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e-3)
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
 def main():
     args = parse()
     dims = tuple(int(v) for v in args.dims.split(","))
     if args.cpu_only:
-        cpu_baseline_child(dims, int(args.delta), args.ell)
+        cpu_baseline_child(dims, int(args.delta), args.ell, args.cpu_data, args.cpu_seed)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the whole lattice lives in one MI355X's HBM and this build "
@@ -336,13 +478,15 @@ def main():
         sys.exit(2)
 
     if args.mode == "kernels":
-        kernels_mode(dims, args.prec)
+        kernels_mode(dims, args.prec, tuple(int(v) for v in args.shape.split(",")) if args.shape else None)
         return
     if args.mode == "learned":
         os.environ.setdefault("OVL_LOG", "1")
         learned_mode(args, dims)
         return
     os.environ.setdefault("OVL_LOG", "1")  # solver progress lines on stderr
+    import tempfile
+
     import numpy as np
     import torch
 
@@ -350,7 +494,8 @@ def main():
     from paper_1106_4964_amd import ovl
 
     dev = torch.device("cuda:0")
-    rho, masses = 1.5, (0.01, 0.05)
+    rho = 1.5
+    masses = tuple(float(v) for v in args.cg_masses.split(","))
     prec = ovl.PREC[args.prec]
     R = 12
     t_setup = time.perf_counter()
@@ -359,6 +504,11 @@ def main():
     g = ovl.Geometry(dims)
     U = si.gauge_field(dims, 0.25, 3)
     gauge = ovl.Gauge(g, torch.from_numpy(U).to(dev))
+    cpu_dir = None
+    if not args.no_cpu:
+        # the CPU baseline's processes read the same links from a file
+        cpu_dir = tempfile.mkdtemp(prefix="ovl_bench_")
+        np.save(os.path.join(cpu_dir, "links.npy"), U)
     del U
     gauge.set_repr(prec, 1)
     gauge.set_repr(ovl.OVL_F32, 1)
@@ -381,9 +531,9 @@ def main():
     log("setup %.1f s" % t_setup)
 
     # ---------------------------------------------------------------- steps
-    def step():
-        ovl.ovl_overlap_apply(y1, bP, gauge, rho, masses[0], sgn, lm, 0, prec, R, None)
-        ovl.ovl_overlap_apply(y2, y1, gauge, rho, masses[0], sgn, lm, 1, prec, R, None)
+    def step(p=prec, xin=bP, a=y1, b=y2):
+        ovl.ovl_overlap_apply(a, xin, gauge, rho, masses[0], sgn, lm, 0, p, R, None)
+        ovl.ovl_overlap_apply(b, a, gauge, rho, masses[0], sgn, lm, 1, p, R, None)
 
     for _ in range(args.warmup):
         step()
@@ -400,30 +550,29 @@ def main():
         n_l, ms_l = ovl.stencil_timer_read(prec, 1, nv, R)
         if n_l:
             step_kernels[nv] = (n_l, ms_l)
-            log("timed steps: stencil f16-12 %d rhs, %d extra vectors: %d launches, avg %.1f us, %.1f%% of step time"
-                % (R, nv, n_l, 1e3 * ms_l / n_l, 100.0 * ms_l / (1e3 * t_steps)))
+            log("timed steps: stencil %s-12 %d rhs, %d extra vectors: %d launches, avg %.1f us, %.1f%% of step time"
+                % (args.prec, R, nv, n_l, 1e3 * ms_l / n_l, 100.0 * ms_l / (1e3 * t_steps)))
     ms_per_step = 1e3 * t_steps / args.steps
     applies_per_s = 2 * R * args.steps / t_steps
     log("step %.2f ms -> %.1f D_ov applies/s" % (ms_per_step, applies_per_s))
 
+    # the same step with BF16 storage (two timed steps)
+    gauge.set_repr(ovl.OVL_BF16, 1)
+    bB = torch.empty(g.spinor_bytes(ovl.OVL_BF16, R), dtype=torch.uint8, device=dev)
+    ovl.ovl_convert(g, b64, ovl.OVL_F64, bB, ovl.OVL_BF16, R, None)
+    zB1, zB2 = torch.empty_like(bB), torch.empty_like(bB)
+    step(ovl.OVL_BF16, bB, zB1, zB2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(2):
+        step(ovl.OVL_BF16, bB, zB1, zB2)
+    torch.cuda.synchronize()
+    bf16_applies = 2 * R * 2 / (time.perf_counter() - t0)
+    log("BF16 storage: %.1f D_ov applies/s" % bf16_applies)
+    del bB, zB1, zB2
+
     # ------------------------------------------------------------- dslash
     N = g.N
-    reals_per_link = 12
-
-    def stencil_time(p, nrhs, reps=20):
-        x = torch.empty(g.spinor_bytes(p, nrhs), dtype=torch.uint8, device=dev)
-        ovl.ovl_convert(g, b64[: g.spinor_bytes(ovl.OVL_F64, nrhs)], ovl.OVL_F64, x, p, nrhs, None)
-        y = torch.empty_like(x)
-        ovl.ovl_hw_apply(y, x, gauge, rho, p, nrhs, None)
-        s = torch.cuda.current_stream()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(s)
-        for _ in range(reps):
-            ovl.ovl_hw_apply(y, x, gauge, rho, p, nrhs, None)
-        e1.record(s)
-        e1.synchronize()
-        return e0.elapsed_time(e1) / reps * 1e-3  # seconds per launch
-
     bytes_per_real = {ovl.OVL_F64: 8, ovl.OVL_F32: 4, ovl.OVL_F16: 2, ovl.OVL_BF16: 2}
 
     def model_bytes(p, L, nrhs, nv=0):
@@ -431,6 +580,7 @@ def main():
         # each input and output spinor once, each extra epilogue vector once
         return N * bytes_per_real[p] * (4 * L + 48 * nrhs + 24 * nv * nrhs)
 
+    scratch = torch.empty(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB
     dslash = {}
     gauge.set_repr(ovl.OVL_F64, 0)
     for p in (ovl.OVL_F32, ovl.OVL_F16, ovl.OVL_BF16):
@@ -439,12 +589,21 @@ def main():
                              ("f32_12_1rhs", ovl.OVL_F32, 12, 1), ("f32_12_12rhs", ovl.OVL_F32, 12, 12),
                              ("f16_12_1rhs", ovl.OVL_F16, 12, 1), ("f16_12_12rhs", ovl.OVL_F16, 12, 12),
                              ("bf16_12_1rhs", ovl.OVL_BF16, 12, 1), ("bf16_12_12rhs", ovl.OVL_BF16, 12, 12)]:
-        t = stencil_time(p, nrhs)
-        gbs = model_bytes(p, L, nrhs) / t / 1e9
-        dslash[name] = {"us": round(t * 1e6, 2), "model_GBps": round(gbs, 1),
+        x = torch.empty(g.spinor_bytes(p, nrhs), dtype=torch.uint8, device=dev)
+        ovl.ovl_convert(g, b64[: g.spinor_bytes(ovl.OVL_F64, nrhs)], ovl.OVL_F64, x, p, nrhs, None)
+        y = torch.empty_like(x)
+        fn = lambda: ovl.ovl_hw_apply(y, x, gauge, rho, p, nrhs, None)  # noqa: E731
+        t = _event_time(fn, 20)
+        tc = _event_time_cold(fn, 20, scratch)
+        mb = model_bytes(p, L, nrhs)
+        dslash[name] = {"us": round(t * 1e6, 2), "model_GBps": round(mb / t / 1e9, 1),
+                        "cold_us": round(tc * 1e6, 2), "cold_model_GBps": round(mb / tc / 1e9, 1),
                         "gflops": round(1368.0 * N * nrhs / t / 1e9, 1),
                         "shape": list(ovl.stencil_shape(g, p, p != ovl.OVL_F64, 0, nrhs))}
-        log("dslash %s: %.1f us, %.0f GB/s (model bytes)" % (name, t * 1e6, gbs))
+        log("dslash %s: warm %.1f us (%.0f GB/s), cold %.1f us (%.0f GB/s) (model bytes)"
+            % (name, t * 1e6, mb / t / 1e9, tc * 1e6, mb / tc / 1e9))
+        del x, y
+    del scratch
     # dominant kernel of the timed steps: the stencil configuration with the
     # largest summed launch time, its average launch measured with HIP events
     dom_nv = max(step_kernels, key=lambda k: step_kernels[k][1])
@@ -462,7 +621,8 @@ def main():
         "unit": "GB/s",
         "frac": round(dom_gbs / HBM_PEAK_GBS, 4),
         "traffic": traffic,
-        "kernel": "stencil_kernel<F16, 12-real links, %d extra vectors>, %d rhs, %s" % (dom_nv, R, "x".join(map(str, dims))),
+        "kernel": "stencil_kernel<%s, 12-real links, %d extra vectors>, %d rhs, %s"
+                  % (args.prec.upper(), dom_nv, R, "x".join(map(str, dims))),
         "bytes_per_launch": dom_bytes,
         "avg_launch_us": round(dom_us, 2),
         "launches": n_dom,
@@ -481,33 +641,61 @@ def main():
             log("inner sign: n = %d (delta %.1e)" % (sgn_in.n, sgn_in.delta))
             cg["inner_sign_order"] = sgn_in.n
 
-        def solve(p, nrhs, m, graph, inner_tol, inner_sign=None):
+        def solve(p, nrhs, m, graph, inner_tol, inner_sign=None, maxiter=20000):
             x = torch.zeros(g.spinor_bytes(ovl.OVL_F64, nrhs), dtype=torch.uint8, device=dev)
             opts = ovl.SolveOpts(p, inner_tol, graph, 1, 60, None, None, 0,
                                  inner_sign.handle.value if inner_sign is not None else None)
             st = ovl.SolveStats()
             rc = ovl.ovl_cg_solve(x, b64[: g.spinor_bytes(ovl.OVL_F64, nrhs)], nrhs, gauge, rho, m, sgn, lm,
-                                  1e-10, 20000, opts, st, None)
+                                  1e-10, maxiter, opts, st, None)
             res = max(st.true_residual[r] for r in range(nrhs))
             return {"rc": rc, "seconds": round(st.seconds, 3), "iterations": st.iterations,
                     "restarts": st.restarts, "max_true_residual": res, "sign_applies": st.sign_applies}
 
-        for m in [float(v) for v in args.cg_masses.split(",")]:
+        for m in masses:
             r_mixed = solve(prec, R, m, args.graph_chunk, args.inner_tol, sgn_in)
             log("CG mixed m=%.2f: %s" % (m, r_mixed))
-            cg["mixed_f16_12rhs_m%.2f" % m] = r_mixed
+            cg["mixed_%s_12rhs_m%.2f" % (args.prec, m)] = r_mixed
+        m0 = masses[0]
         if args.fp64_cg_rhs > 0:
             nfp = min(R, args.fp64_cg_rhs)
-            m0 = float(args.cg_masses.split(",")[0])
             r64 = solve(ovl.OVL_F64, nfp, m0, 0, 0.0)
             log("CG plain FP64 m=%.2f (%d rhs): %s" % (m0, nfp, r64))
             cg["plain_f64_m%.2f_%drhs" % (m0, nfp)] = r64
-            t64 = r64["seconds"] * (R / nfp)
-            cg["plain_f64_12rhs_seconds"] = round(t64, 2)
-            cg["speedup_vs_plain_f64_m%.2f" % m0] = round(t64 / cg["mixed_f16_12rhs_m%.2f" % m0]["seconds"], 2)
-            if nfp < R:
-                cg["note"] = ("plain FP64 time measured on %d of the 12 point sources and scaled by 12/%d "
-                              "(FP64 solves gain nothing from batching)" % (nfp, nfp))
+            t_sep = r64["seconds"] * (R / nfp)
+            cg["plain_f64_12rhs_separate_seconds"] = round(t_sep, 2)
+            if args.fp64_batched_iters > 0:
+                # the 12 sources as one FP64 batch: the time per inner iteration
+                # from two capped solves (k1 and k2 iterations; their fixed costs
+                # - FP64 true residuals, first direction - cancel in the difference)
+                k2 = max(2, args.fp64_batched_iters)
+                k1 = max(1, k2 // 3)
+                r1 = solve(ovl.OVL_F64, R, m0, 0, 0.0, maxiter=k1)
+                r2 = solve(ovl.OVL_F64, R, m0, 0, 0.0, maxiter=k2)
+                per_it = (r2["seconds"] - r1["seconds"]) / max(1, r2["iterations"] - r1["iterations"])
+                t_bat = r2["seconds"] + per_it * max(0, r64["iterations"] - r2["iterations"])
+                cg["plain_f64_12rhs_batched"] = {
+                    "seconds_extrapolated": round(t_bat, 2), "seconds_per_iteration": round(per_it, 4),
+                    "iterations_timed": [r1["iterations"], r2["iterations"]],
+                    "iterations_assumed": r64["iterations"],
+                    "note": ("the 12 point sources solved as one FP64 batch: time per inner iteration from solves "
+                             "capped at %d and %d iterations, extended to the iteration count of the full FP64 "
+                             "solve of one source (the 12 sources differ only in spin and colour)"
+                             % (r1["iterations"], r2["iterations"]))}
+                log("CG plain FP64 12 rhs batched: %.3f s per iteration -> %.1f s (extrapolated)" % (per_it, t_bat))
+                t_den = t_bat
+                cg["denominator"] = "plain FP64 CG on the 12 sources as one batch (extrapolated, see above)"
+            else:
+                t_den = t_sep
+                cg["denominator"] = "plain FP64 CG, one source timed, times 12"
+            key = "mixed_%s_12rhs_m%.2f" % (args.prec, m0)
+            cg["speedup_vs_plain_f64_m%.2f" % m0] = round(t_den / cg[key]["seconds"], 2)
+            cg["speedup_vs_plain_f64_separate_m%.2f" % m0] = round(t_sep / cg[key]["seconds"], 2)
+
+    c2 = None
+    if not args.no_c2:
+        log("C2 block (16x16x16x32)")
+        c2 = c2_block(ovl, args)
 
     lib_live, lib_peak = ctypes.c_int64(), ctypes.c_int64()
     ovl.ovl_mem_stats(ctypes.byref(lib_live), ctypes.byref(lib_peak), 0)
@@ -520,7 +708,13 @@ def main():
     cpu = None
     if not args.no_cpu:
         log("cpu baseline (oracle)")
-        cpu = cpu_baseline(dims, sgn.n, ell)
+        try:
+            cpu = cpu_baseline(dims, sgn.n, ell, cpu_dir)
+        finally:
+            import shutil
+
+            shutil.rmtree(cpu_dir, ignore_errors=True)
+        log("cpu baseline: %s" % cpu)
 
     out = {
         "metric": METRIC,
@@ -545,8 +739,10 @@ def main():
         },
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "bf16_applies_per_s": round(bf16_applies, 3),
         "dslash": dslash,
         "cg": cg,
+        "c2_16x16x16x32": c2,
         "memory": memory,
     }
     print(json.dumps(out), flush=True)
