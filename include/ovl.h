@@ -73,6 +73,7 @@ typedef struct ovl_gauge ovl_gauge;
 typedef struct ovl_sign ovl_sign;
 typedef struct ovl_lowmodes ovl_lowmodes;
 typedef struct ovl_net ovl_net;
+typedef struct ovl_deflation ovl_deflation;
 
 const char* ovl_last_error(void);
 int ovl_version(void);
@@ -262,6 +263,12 @@ int ovl_overlap_apply(void* out, const void* in, const ovl_gauge* u, double rho,
  *   with an accurate sign, not with FP16 storage at small m.  A cycle that
  *   breaks down or does not halve the true residual switches the rest of
  *   the solve to D D^dag.  Not with harvesting.
+ *   opts->deflation (eq. 9): at every FP64 correction cycle the true
+ *   residual r is split along the deflation's eigenvectors xi_i of D: x gets
+ *   sum_i xi_i (xi_i^dag r) / (rho d_i + m (1 - d_i/2)) at once and the inner
+ *   CG solves only for r minus its components along the xi_i, at the reduced
+ *   condition number ||D|| / |d_l'|; the cycles repeat until the FP64 true
+ *   residual meets tol, so approximate eigenpairs only cost extra cycles.
  *   opts may be NULL (plain FP64, no graph).  Work is done on a private
  *   stream ordered after, and before, the caller's stream s.
  * ovl_propagator: out = (1 - D/2) x (Sec. II), the propagator from a
@@ -281,6 +288,9 @@ typedef struct {
                                  a lower order); NULL = the outer one.  The
                                  FP64 true residual always uses `sign`.   */
   int chiral;          /* CG only: 1 = inner solves in one chiral sector   */
+  const ovl_deflation* deflation; /* CG only: eigenpairs of D deflated in
+                                     every defect-correction cycle (eq. 9);
+                                     NULL = none.  Not with chiral.       */
 } ovl_solve_opts;
 
 typedef struct {
@@ -368,6 +378,36 @@ int ovl_hw_eigs(const ovl_gauge* u, double rho, int ell, int m, void* V, double*
  * eigensolver uses for its Gram and Rayleigh-Ritz matrices.
  */
 int ovl_host_heev(int n, const double* A, double* w, double* V);
+
+/* ovl_overlap_eigs: eigenpairs of the massless overlap operator
+ *   D = 1 + gamma5 sign(H_w) (eq. 3) closest to zero, computed in one chiral
+ *   sector as the paper does (Sec. V): thick-restart Lanczos (FP64, full
+ *   re-orthogonalisation, basis of K <= 512 vectors) on the Hermitian
+ *   K_s = s P_s sign(H_w) P_s, P_s = (1 + s gamma5)/2, s = sector (+1 or -1),
+ *   each matvec one sign application with `sign` and `lowmodes`.  The ell
+ *   lowest eigenvectors v (eigenvalue k) of K_s give, with
+ *   w = P_{-s} sign(H_w) v, sn = ||w|| and u = w/sn, the eigenpairs
+ *   xi = (v +- i u)/sqrt(2), d = 1 + k +- i s sn of D (a real mode, sn = 0,
+ *   gives xi = v, d = 1 + k): up to 2*ell pairs, ordered by |d| and, within a
+ *   pair, negative imaginary part first; *nout receives their number.
+ *   V: caller-owned device buffer of at least 2*ell FP64 spinors; V[:, 0]
+ *   holds the start vector on entry (its sector-s part is used), V[:, 0..
+ *   *nout) the orthonormal eigenvectors on exit.  d: host array of 4*ell
+ *   doubles, (re, im) per pair.  Stops when the Ritz residuals of the ell
+ *   sector vectors are <= tol or after max_iter restart cycles
+ *   (OVL_W_NOT_CONVERGED); stats->max_residual is the recomputed
+ *   ||K_s v - k v||, stats->hw_applies counts D_w applications.  Device
+ *   workspace: K + 3 FP64 spinors.
+ * ovl_deflation_create: n eigenpairs (xi_i, d_i) of D for the deflated CG
+ *   (ovl_solve_opts.deflation, eq. 9).  Xi: n orthonormal FP64 spinors,
+ *   caller-owned device memory BORROWED for the handle's lifetime; d: host
+ *   array of 2n doubles (copied).  OVL_E_NAN for a non-finite eigenvalue.
+ */
+int ovl_overlap_eigs(const ovl_gauge* u, double rho, const ovl_sign* sign, const ovl_lowmodes* lowmodes, int sector,
+                     int ell, int K, void* V, double* d, int* nout, double tol, int max_iter, ovl_eig_stats* stats,
+                     ovl_stream_t s);
+int ovl_deflation_create(const ovl_geom* g, int n, const void* Xi, const double* d, ovl_deflation** out);
+int ovl_deflation_destroy(ovl_deflation* df);
 
 /* --------------------------------------------------- learned preconditioner
  * A 2-layer gauge-equivariant parallel-transport convolution network

@@ -81,6 +81,18 @@ def sector_lowest(apply_eps, N: int, s: int, count: int):
     return w[:count].copy(), V
 
 
+def sector_lowest_dense(E: np.ndarray, N: int, s: int, count: int):
+    """sector_lowest for a dense eps (matrix E on [N, 4, 3] fields flattened in
+    C order): K_s is s times the submatrix of E on the sector's components."""
+    spins = (0, 1) if s > 0 else (2, 3)
+    idx = np.array([12 * site + 3 * sp + c for site in range(N) for sp in spins for c in range(3)])
+    M = s * E[np.ix_(idx, idx)]
+    w, X = np.linalg.eigh(0.5 * (M + M.conj().T))
+    V = np.zeros((count, N * 12), dtype=np.complex128)
+    V[:, idx] = X[:, :count].T
+    return w[:count].copy(), V.reshape(count, N, 4, 3)
+
+
 def overlap_pairs(apply_eps, k: np.ndarray, V: np.ndarray, s: int, real_tol: float = 1e-9):
     """Eigenpairs (d, xi) of D = 1 + gamma5 eps from sector eigenpairs (k, v)
     of K_s.  Returns (d [n], Xi [n, N, 4, 3]) ordered by (|d|, arg d); a

@@ -564,6 +564,14 @@ struct ovl_lowmodes {
   double* dev_sign = nullptr;  // sign(lambda_i) on the device
 };
 
+// Eigenpairs of the massless overlap operator used to deflate D(m) (eq. 9).
+struct ovl_deflation {
+  ovl_geom geom;
+  int n;
+  const void* Xi;                       // borrowed: n FP64 spinors
+  std::vector<std::complex<double>> d;  // eigenvalues of D
+};
+
 struct ovl_net {
   ovl_geom geom;
   int hidden;

@@ -99,6 +99,15 @@ void overlap_combine(void* out, const void* in, const ovl_gauge* u, double rho, 
 void overlap_combine_dag(void* out, const void* in, const ovl_gauge* u, double rho, double ap, double am,
                          const ovl_sign* sg, const ovl_lowmodes* lm, int prec, int nrhs, hipStream_t s);
 
+// The low part of eq. 9 for a batch of R FP64 residuals:
+// x += sum_i xi_i (xi_i^dag r) / (rho d_i + m (1 - d_i/2)),  r -= sum_i xi_i (xi_i^dag r).
+void deflate(const ovl_deflation* df, double rho, double m, void* x, void* r, int R, hipStream_t s);
+
+// Eigen-decomposition of a Hermitian n x n matrix (column-major) on the
+// host: ascending eigenvalues w, eigenvectors V (column-major).
+void host_heev(int n, std::vector<std::complex<double>> A, std::vector<double>& w,
+               std::vector<std::complex<double>>& V);
+
 int cg_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, double m, const ovl_sign* sg,
              const ovl_lowmodes* lm, double tol, int maxiter, const ovl_solve_opts* o, ovl_solve_stats* st,
              hipStream_t us);

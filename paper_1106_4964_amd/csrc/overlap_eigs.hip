@@ -1,0 +1,294 @@
+// Low eigenpairs of the massless overlap operator from one chiral sector,
+// and the deflation handle (arXiv:1106.4964 Sec. II eq. 9, Sec. V).
+//
+// D = 1 + gamma5 eps with eps = sign(H_w) (eq. 3).  gamma5 D = gamma5 + eps is
+// Hermitian; on the chiral sector s (P_s = (1 + s gamma5)/2, spins 0-1 for
+// s = +1, 2-3 for s = -1 in the chiral basis) its eigenvectors are those of
+// K_s = s P_s eps P_s, whose eigenvalues k lie in [-1, 1].  The paper
+// computes the overlap eigenvectors this way (Sec. V).  An eigenvector v of
+// K_s gives, with w = P_{-s} eps v, sn = ||w|| = sqrt(1 - k^2) and u = w / sn,
+// the invariant plane span(v, u) on which D has the eigenpairs
+//     xi_+- = (v +- i u) / sqrt(2),   d_+- = 1 + k +- i s sn,
+// and |d|^2 = 2 (1 + k): the modes closest to zero are the lowest k.  A real
+// mode (sn = 0) gives d = 1 + k and xi = v.
+//
+// Krylov method: thick-restart Lanczos on K_s (FP64, full
+// re-orthogonalisation, each matvec one sign application of the polynomial
+// approximation with the low modes of H_w projected exactly, eq. 7), Ritz
+// residuals from the Lanczos relation, the final ones recomputed from the
+// same sign application that gives u.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+
+#include "ops.h"
+
+namespace ovl {
+
+using zc = std::complex<double>;
+
+namespace {
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t n = 0;
+  explicit DevBuf(size_t bytes) : n(bytes) {
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error(OVL_E_NOMEM, "overlap eigensolver: device allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+    mem_track(static_cast<int64_t>(n));
+  }
+  ~DevBuf() {
+    if (p) {
+      (void)hipFree(p);
+      mem_track(-static_cast<int64_t>(n));
+    }
+  }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+};
+
+char* vat(void* base, size_t v64, int i) { return static_cast<char*>(base) + static_cast<size_t>(i) * v64; }
+
+}  // namespace
+}  // namespace ovl
+
+using namespace ovl;
+
+extern "C" {
+
+int ovl_overlap_eigs(const ovl_gauge* u, double rho, const ovl_sign* sgn, const ovl_lowmodes* lm, int sector, int ell,
+                     int K, void* V, double* d, int* nout, double tol, int max_iter, ovl_eig_stats* stats,
+                     ovl_stream_t st) {
+  return guard([&] {
+    OVL_REQUIRE(u && sgn && V && d && nout && stats, OVL_E_ARG, "null argument");
+    OVL_REQUIRE(sector == 1 || sector == -1, OVL_E_ARG, "sector must be +1 or -1");
+    OVL_REQUIRE(ell >= 1 && K >= ell + 8 && K <= 512, OVL_E_ARG, "need ell >= 1 and ell + 8 <= K <= 512");
+    OVL_REQUIRE(tol > 0.0 && max_iter >= 1, OVL_E_ARG, "need tol > 0 and max_iter >= 1");
+    if (lm && lm->ell == 0) lm = nullptr;
+    if (lm) OVL_REQUIRE(lm->geom.N == u->geom.N, OVL_E_ARG, "low modes and gauge field have different lattices");
+    const auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = static_cast<hipStream_t>(st);
+    const ovl_geom* g = &u->geom;
+    const size_t v64 = spinor_vec_bytes(g, OVL_F64);
+    const size_t N = static_cast<size_t>(g->N);
+    *stats = ovl_eig_stats{};
+    const int keep = std::max(ell + 4, std::min(K - 4, ell + (K - ell) / 2));  // thick-restart size
+
+    DevBuf Q(v64 * (K + 1)), w(v64), t(v64);
+    DevBuf sc(sizeof(double) * 4 + sizeof(int) * 2);
+    double* dsc = static_cast<double*>(sc.p);
+    int* dsect = reinterpret_cast<int*>(dsc + 4);
+    WsBuf cb(sizeof(double2) * (K + 1), s);
+    DevBuf Sdev(sizeof(double2) * static_cast<size_t>(K) * K);
+    const int hsect[2] = {sector, -sector};
+    OVL_HIP(hipMemcpyAsync(dsect, hsect, sizeof(hsect), hipMemcpyHostToDevice, s));
+
+    auto norm = [&](const void* x) {
+      blas_norm2(OVL_F64, v64 / 16, x, 1, v64, dsc, s);
+      double h[2];
+      OVL_HIP(hipMemcpyAsync(h, dsc, sizeof(h), hipMemcpyDeviceToHost, s));
+      OVL_HIP(hipStreamSynchronize(s));
+      return std::sqrt(h[0]);
+    };
+    // y = a x (+ b y), complex host scalars
+    auto axpby = [&](const void* x, zc a, void* y, bool keep_y, zc b = zc(1.0, 0.0)) {
+      const double h[4] = {a.real(), a.imag(), b.real(), b.imag()};
+      OVL_HIP(hipMemcpyAsync(dsc, h, sizeof(h), hipMemcpyHostToDevice, s));
+      blas_axpby(OVL_F64, x, dsc, OVL_F64, y, keep_y ? dsc + 2 : nullptr, N, 1, s);
+      OVL_HIP(hipStreamSynchronize(s));  // the host scalars are reused
+    };
+    // out = eps in (FP64), counted
+    auto eps = [&](void* out, const void* in) {
+      overlap_apply(out, in, u, rho, 0.0, sgn, lm, 0, OVL_F64, 1, s);
+      stats->hw_applies += 2 * (static_cast<int64_t>(sgn->c.size()) - 1) + 1;
+    };
+    // out = K_s in = s P_s eps in
+    auto apply_K = [&](void* out, const void* in) {
+      eps(t.p, in);
+      blas_chiral(OVL_F64, v64, t.p, 1, dsect, s);
+      axpby(t.p, zc(sector, 0.0), out, false);
+    };
+    auto upload_S = [&](const std::vector<zc>& S, int rows, int cols) {
+      std::vector<double2> h(static_cast<size_t>(rows) * cols);
+      for (size_t i = 0; i < h.size(); ++i) h[i] = make_double2(S[i].real(), S[i].imag());
+      OVL_HIP(hipMemcpyAsync(Sdev.p, h.data(), h.size() * sizeof(double2), hipMemcpyHostToDevice, s));
+      OVL_HIP(hipStreamSynchronize(s));
+    };
+
+    // q_0: the caller's start vector, projected to the sector
+    OVL_HIP(hipMemcpyAsync(Q.p, V, v64, hipMemcpyDeviceToDevice, s));
+    blas_chiral(OVL_F64, v64, Q.p, 1, dsect, s);
+    {
+      const double n0 = norm(Q.p);
+      OVL_REQUIRE(n0 > 0.0 && std::isfinite(n0), OVL_E_ARG, "start vector has no component in the sector");
+      axpby(Q.p, zc(1.0 / n0, 0.0), Q.p, false);
+    }
+    std::vector<zc> T(static_cast<size_t>(K + 1) * (K + 1), zc(0.0, 0.0));
+    auto Tat = [&](int i, int j) -> zc& { return T[i + static_cast<size_t>(K + 1) * j]; };
+    std::vector<double2> hc(K + 1), hc2(K + 1);
+    std::vector<double> th;
+    std::vector<zc> S;
+    int cur = 0;
+    double worst = INFINITY;
+    for (int cycle = 0;; ++cycle) {
+      for (int j = cur; j < K; ++j) {
+        apply_K(w.p, vat(Q.p, v64, j));
+        for (int i = 0; i <= j; ++i) hc2[i] = make_double2(0.0, 0.0);
+        for (int pass = 0; pass < 2; ++pass) {  // w -= Q (Q^dag w), twice
+          block_dot(g, Q.p, j + 1, w.p, OVL_F64, 1, static_cast<double2*>(cb.p), s);
+          OVL_HIP(hipMemcpyAsync(hc.data(), cb.p, sizeof(double2) * (j + 1), hipMemcpyDeviceToHost, s));
+          OVL_HIP(hipStreamSynchronize(s));
+          for (int i = 0; i <= j; ++i) {
+            hc2[i] = make_double2(hc2[i].x + hc[i].x, hc2[i].y + hc[i].y);
+            hc[i] = make_double2(-hc[i].x, -hc[i].y);
+          }
+          OVL_HIP(hipMemcpyAsync(cb.p, hc.data(), sizeof(double2) * (j + 1), hipMemcpyHostToDevice, s));
+          block_axpy(g, Q.p, j + 1, static_cast<const double2*>(cb.p), w.p, OVL_F64, 1, true, s);
+          OVL_HIP(hipStreamSynchronize(s));
+        }
+        for (int i = 0; i <= j; ++i) Tat(i, j) = zc(hc2[i].x, hc2[i].y);
+        const double beta = norm(w.p);
+        OVL_REQUIRE(std::isfinite(beta), OVL_E_NAN, "overlap eigensolver: NaN in the Lanczos recurrence");
+        if (beta == 0.0) throw Error(OVL_E_BREAKDOWN, "overlap eigensolver: invariant subspace found before K steps");
+        Tat(j + 1, j) = beta;
+        axpby(w.p, zc(1.0 / beta, 0.0), vat(Q.p, v64, j + 1), false);
+      }
+      // Ritz pairs, lowest first; residual ||K y - theta y|| = beta_K |s_{K-1}|
+      std::vector<zc> Tk(static_cast<size_t>(K) * K);
+      for (int j = 0; j < K; ++j)
+        for (int i = 0; i < K; ++i) Tk[i + static_cast<size_t>(K) * j] = 0.5 * (Tat(i, j) + std::conj(Tat(j, i)));
+      host_heev(K, Tk, th, S);
+      const double betaK = Tat(K, K - 1).real();
+      worst = 0.0;
+      for (int i = 0; i < ell; ++i) worst = std::max(worst, betaK * std::abs(S[(K - 1) + static_cast<size_t>(K) * i]));
+      stats->iterations = cycle + 1;
+      if (log_on())
+        fprintf(stderr, "[ovl overlap eigs] cycle %d (basis %d): max Ritz residual %.3e, k_%d = %.6f\n", cycle, K, worst,
+                ell, th[ell - 1]);
+      if (worst <= tol || cycle + 1 >= max_iter) break;
+      // thick restart: the `keep` lowest Ritz vectors and the residual direction
+      upload_S(S, K, K);
+      block_rotate_inplace(g, Q.p, K, static_cast<const double2*>(Sdev.p), keep, s);
+      OVL_HIP(hipMemcpyAsync(vat(Q.p, v64, keep), vat(Q.p, v64, K), v64, hipMemcpyDeviceToDevice, s));
+      std::fill(T.begin(), T.end(), zc(0.0, 0.0));
+      for (int i = 0; i < keep; ++i) {
+        Tat(i, i) = th[i];
+        const zc c = betaK * S[(K - 1) + static_cast<size_t>(K) * i];
+        Tat(keep, i) = c;
+        Tat(i, keep) = std::conj(c);
+      }
+      cur = keep;
+    }
+    // the ell lowest Ritz vectors, then the pairs of D from each of them;
+    // vector i of the sector sits in Q[i] after the rotation
+    upload_S(S, K, K);
+    block_rotate_inplace(g, Q.p, K, static_cast<const double2*>(Sdev.p), ell, s);
+    int n = 0;
+    double max_res = 0.0;
+    const double r2 = 1.0 / std::sqrt(2.0);
+    for (int i = 0; i < ell; ++i) {
+      void* v = vat(Q.p, v64, i);
+      eps(t.p, v);
+      // w = P_{-s} eps v (the partner direction), t = P_s eps v
+      OVL_HIP(hipMemcpyAsync(w.p, t.p, v64, hipMemcpyDeviceToDevice, s));
+      blas_chiral(OVL_F64, v64, w.p, 1, dsect + 1, s);
+      blas_chiral(OVL_F64, v64, t.p, 1, dsect, s);
+      // explicit residual ||s P_s eps v - k v||
+      axpby(v, zc(-sector * th[i], 0.0), t.p, true);
+      max_res = std::max(max_res, norm(t.p));
+      const double sn = norm(w.p);
+      const double k = std::min(1.0, std::max(-1.0, th[i]));
+      if (sn <= 1e-9) {  // real mode of chirality `sector`
+        OVL_HIP(hipMemcpyAsync(vat(V, v64, n), v, v64, hipMemcpyDeviceToDevice, s));
+        d[2 * n] = 1.0 + k;
+        d[2 * n + 1] = 0.0;
+        ++n;
+        continue;
+      }
+      // xi = (v + sg i u)/sqrt(2), d = 1 + k + sg i s sn; negative imaginary part first
+      for (int half = 0; half < 2; ++half) {
+        const int sg = (half == 0) ? -sector : sector;
+        void* xo = vat(V, v64, n);
+        axpby(v, zc(r2, 0.0), xo, false);
+        axpby(w.p, zc(0.0, sg * r2 / sn), xo, true);
+        d[2 * n] = 1.0 + k;
+        d[2 * n + 1] = sg * sector * sn;
+        ++n;
+      }
+    }
+    OVL_HIP(hipStreamSynchronize(s));
+    *nout = n;
+    stats->max_residual = max_res;
+    stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (log_on())
+      fprintf(stderr, "[ovl overlap eigs] %d eigenpairs of D from %d sector vectors, max residual %.3e, %.1f s\n", n,
+              ell, max_res, stats->seconds);
+    return max_res <= tol ? OVL_OK : OVL_W_NOT_CONVERGED;
+  });
+}
+
+int ovl_deflation_create(const ovl_geom* g, int n, const void* Xi, const double* d, ovl_deflation** out) {
+  return guard([&] {
+    OVL_REQUIRE(g && Xi && d && out, OVL_E_ARG, "null argument");
+    OVL_REQUIRE(n >= 1 && n <= 4096, OVL_E_ARG, "need 1 <= n <= 4096 eigenpairs");
+    ovl_deflation* df = new ovl_deflation;
+    df->geom = *g;
+    df->n = n;
+    df->Xi = Xi;
+    df->d.resize(n);
+    for (int i = 0; i < n; ++i) {
+      df->d[i] = zc(d[2 * i], d[2 * i + 1]);
+      if (!std::isfinite(d[2 * i]) || !std::isfinite(d[2 * i + 1])) {
+        delete df;
+        throw Error(OVL_E_NAN, "non-finite eigenvalue");
+      }
+    }
+    *out = df;
+    return OVL_OK;
+  });
+}
+
+int ovl_deflation_destroy(ovl_deflation* df) {
+  delete df;
+  return OVL_OK;
+}
+
+}  // extern "C"
+
+namespace ovl {
+
+// The low part of eq. 9 for a batch of FP64 residuals r (R vectors):
+// x += sum_i xi_i (xi_i^dag r) / (rho d_i + m (1 - d_i / 2)),
+// r -= sum_i xi_i (xi_i^dag r).
+void deflate(const ovl_deflation* df, double rho, double m, void* x, void* r, int R, hipStream_t s) {
+  const ovl_geom* g = &df->geom;
+  const int n = df->n;
+  WsBuf cbuf(sizeof(double2) * static_cast<size_t>(n) * R, s);
+  double2* C = static_cast<double2*>(cbuf.p);
+  block_dot(g, df->Xi, n, r, OVL_F64, R, C, s);
+  std::vector<double2> h(static_cast<size_t>(n) * R), hx(h.size());
+  OVL_HIP(hipMemcpyAsync(h.data(), C, sizeof(double2) * h.size(), hipMemcpyDeviceToHost, s));
+  OVL_HIP(hipStreamSynchronize(s));
+  for (int i = 0; i < n; ++i) {
+    const zc lam = rho * df->d[i] + m * (1.0 - 0.5 * df->d[i]);
+    for (int r2 = 0; r2 < R; ++r2) {
+      const size_t k = static_cast<size_t>(i) * R + r2;
+      const zc c(h[k].x, h[k].y);
+      const zc q = c / lam;
+      hx[k] = make_double2(q.real(), q.imag());
+      h[k] = make_double2(-c.real(), -c.imag());
+    }
+  }
+  WsBuf kx(sizeof(double2) * hx.size(), s), kr(sizeof(double2) * h.size(), s);
+  OVL_HIP(hipMemcpyAsync(kx.p, hx.data(), sizeof(double2) * hx.size(), hipMemcpyHostToDevice, s));
+  OVL_HIP(hipMemcpyAsync(kr.p, h.data(), sizeof(double2) * h.size(), hipMemcpyHostToDevice, s));
+  block_axpy(g, df->Xi, n, static_cast<const double2*>(kx.p), x, OVL_F64, R, true, s);
+  block_axpy(g, df->Xi, n, static_cast<const double2*>(kr.p), r, OVL_F64, R, true, s);
+  OVL_HIP(hipStreamSynchronize(s));  // the host coefficient arrays end with this scope
+}
+
+}  // namespace ovl

@@ -159,6 +159,9 @@ int cg_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, doub
   bool chiral = opt.chiral != 0;
   OVL_REQUIRE(!chiral || !(opt.harvest_x && opt.harvest_b && opt.harvest_cap > 0), OVL_E_ARG,
               "chiral solves do not harvest training pairs");
+  OVL_REQUIRE(!chiral || !opt.deflation, OVL_E_ARG, "chiral solves do not take a deflation");
+  if (opt.deflation)
+    OVL_REQUIRE(opt.deflation->geom.N == u->geom.N, OVL_E_ARG, "deflation and gauge field have different lattices");
 
   Solver S{};
   S.u = u;
@@ -284,6 +287,14 @@ int cg_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, doub
       if (log_on())
         fprintf(stderr, "[ovl cg] cycle %d: %d iterations, max FP64 true residual %.3e\n", st->restarts, its, worst);
       if (done) break;
+      if (opt.deflation) {
+        // eq. 9: the low part of the correction at once; the inner solve is
+        // left with the residual minus its components along the eigenvectors
+        deflate(opt.deflation, rho, m, x, r64.p, R, s);
+        S.norm2(r64.p, OVL_F64, dS->rrn, dS);
+        OVL_HIP(hipMemcpyAsync(rn2.data(), dS->rrn, sizeof(double) * R, hipMemcpyDeviceToHost, s));
+        OVL_HIP(hipStreamSynchronize(s));
+      }
       if (chiral && prev_worst_chiral > 0.0 && worst > 0.5 * prev_worst_chiral) {
         if (log_on()) fprintf(stderr, "[ovl cg] chiral cycle did not halve the residual: switching to D D^dag\n");
         chiral = false;

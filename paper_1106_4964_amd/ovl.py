@@ -82,6 +82,7 @@ class SolveOpts(ctypes.Structure):
         ("harvest_cap", ctypes.c_int),
         ("inner_sign", ctypes.c_void_p),
         ("chiral", ctypes.c_int),
+        ("deflation", ctypes.c_void_p),
     ]
 
 
@@ -160,6 +161,9 @@ _SIGS = {
     "ovl_hw_bound": (P, D, P, I, P, P, P, ST),
     "ovl_hw_eigs": (P, D, I, I, P, P, D, D, I, I, P, ST),
     "ovl_host_heev": (I, P, P, P),
+    "ovl_overlap_eigs": (P, D, P, P, I, I, I, P, P, P, D, I, P, ST),
+    "ovl_deflation_create": (P, I, P, P, P),
+    "ovl_deflation_destroy": (P,),
     "ovl_fgcr_solve": (P, P, I, P, D, D, P, P, P, I, D, I, P, P, ST),
     "ovl_net_create": (P, I, P),
     "ovl_net_destroy": (P,),
@@ -385,6 +389,27 @@ class Net:
             return
         if getattr(self, "handle", None) is not None and self.handle.value:
             _lib.ovl_net_destroy(self.handle)
+            self.handle = None
+
+
+class Deflation:
+    """Borrowed FP64 eigenvectors Xi (device, n packed spinors) and complex eigenvalues d of D."""
+
+    def __init__(self, geom, Xi_dev, d):
+        d = np.ascontiguousarray(np.asarray(d, dtype=np.complex128))
+        h = ctypes.c_void_p()
+        ovl_deflation_create(geom.handle, len(d), Xi_dev, d.view(np.float64), ctypes.byref(h))
+        self.handle = h
+        self.Xi = Xi_dev  # keep the borrowed buffer alive
+        self.n = len(d)
+
+    def __del__(self, _lib=lib, _exiting=sys.is_finalizing):
+        # at interpreter exit module globals may be gone and the process end
+        # releases the device memory anyway
+        if _exiting():
+            return
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            _lib.ovl_deflation_destroy(self.handle)
             self.handle = None
 
 

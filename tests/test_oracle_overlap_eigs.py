@@ -79,6 +79,18 @@ def test_one_sector_gives_the_lowest_pairs_ordered(small):
     assert np.max(np.abs(np.abs(d) - ref[: len(d)])) < 1e-10
 
 
+@pytest.mark.parametrize("sct", [1, -1])
+def test_dense_slice_equals_sector_operator(small, sct):
+    lat, H, E, D, apply_eps = small
+    k1, V1 = oe.sector_lowest(apply_eps, lat.N, sct, 10)
+    k2, V2 = oe.sector_lowest_dense(E, lat.N, sct, 10)
+    assert np.max(np.abs(k1 - k2)) < 1e-13
+    # same invariant subspaces: projector difference
+    P1 = V1.reshape(10, -1).T @ V1.reshape(10, -1).conj()
+    P2 = V2.reshape(10, -1).T @ V2.reshape(10, -1).conj()
+    assert np.max(np.abs(P1 - P2)) < 1e-10
+
+
 def test_free_field_closed_form():
     """U = 1: D(p) = 1 + (M(p) + i gamma.sin p)/omega(p) has the eigenvalues
     1 + (M +- i |sin p|)/omega, each twice per colour (eq. 3 at U = 1)."""
