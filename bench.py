@@ -81,6 +81,8 @@ def parse():
     ap.add_argument("--cpu-data", type=str, default="", help=argparse.SUPPRESS)
     ap.add_argument("--cpu-seed", type=int, default=0, help=argparse.SUPPRESS)
     ap.add_argument("--no-c2", action="store_true", help="skip the 16^3x32 block (C2)")
+    ap.add_argument("--defl-ell", type=int, default=16,
+                    help="16^3x32 block: chiral-sector eigenvectors for the deflated CG (eq. 9); 0 skips it")
     ap.add_argument("--shape", type=str, default="",
                     help="kernels mode: pin the 12-rhs stencil shape kr,bs,pipe,rin,tm for the sign applications")
     ap.add_argument("--fp64-batched-iters", type=int, default=12,
@@ -426,8 +428,55 @@ def c2_block(ovl, args):
         out[name] = rec
     out["cg_speedup_f16_vs_f64"] = round(out["f64"]["cg"]["seconds"] / out["f16"]["cg"]["seconds"], 2)
     out["cg_speedup_f32_vs_f64"] = round(out["f64"]["cg"]["seconds"] / out["f32"]["cg"]["seconds"], 2)
+    if args.defl_ell > 0:
+        out["deflation"] = deflation_block(ovl, g, gauge, rho, m, sgn, sgn_in, lm, b64, args.defl_ell, out)
     del lm, V
     return out
+
+
+def deflation_block(ovl, g, gauge, rho, m, sgn, sgn_in, lm, b64, ell, plain):
+    """Eigenpairs of D closest to zero from ell eigenvectors of one chiral
+    sector (FP64 sign with the projected modes), then the same CG solves as
+    above with eq. 9 deflation, reported beside the undeflated ones."""
+    import ctypes
+
+    import numpy as np
+    import torch
+
+    import synth_inputs as si
+
+    dev = torch.device("cuda:0")
+    V = torch.empty(g.spinor_bytes(ovl.OVL_F64, 2 * ell), dtype=torch.uint8, device=dev)
+    ovl.ovl_pack_spinor(g, torch.from_numpy(si.gaussian_spinor(g.dims, 7)[None]).to(dev), V, ovl.OVL_F64, 1, None)
+    d = np.zeros(4 * ell)
+    nout = ctypes.c_int()
+    est = ovl.EigStats()
+    K = min(512, max(2 * ell + 16, ell + 48))
+    rc = ovl.ovl_overlap_eigs(gauge, rho, sgn, lm, +1, ell, K, V, d, ctypes.byref(nout), 1e-9, 40, ctypes.byref(est),
+                              None)
+    dc = d[: 2 * nout.value].view(np.complex128)
+    rec = {"sector_vectors": ell, "lanczos_basis": K, "pairs_of_D": nout.value, "rc": rc,
+           "eig_seconds": round(est.seconds, 2), "eig_restart_cycles": est.iterations,
+           "eig_dslash_applies": est.hw_applies, "eig_max_residual": est.max_residual,
+           "abs_d_min": float(np.abs(dc[0])), "abs_d_max": float(np.abs(dc[-1]))}
+    defl = ovl.Deflation(g, V, dc)
+    for name, p in (("f64", ovl.OVL_F64), ("f16", ovl.OVL_F16)):
+        xs = torch.zeros(g.spinor_bytes(ovl.OVL_F64), dtype=torch.uint8, device=dev)
+        if p == ovl.OVL_F64:
+            opts = ovl.SolveOpts(p, 0.0, 0, 1, 60)
+        else:
+            opts = ovl.SolveOpts(p, 1e-3, 8, 1, 60, None, None, 0, sgn_in.handle.value)
+        opts.deflation = defl.handle.value
+        st = ovl.SolveStats()
+        rc = ovl.ovl_cg_solve(xs, b64, 1, gauge, rho, m, sgn, lm, 1e-10, 20000, opts, st, None)
+        base = plain[name]["cg"]
+        rec["cg_" + name] = {"rc": rc, "seconds": round(st.seconds, 3), "iterations": st.iterations,
+                             "restarts": st.restarts, "true_residual": st.true_residual[0],
+                             "undeflated_iterations": base["iterations"], "undeflated_seconds": base["seconds"],
+                             "iteration_ratio": round(st.iterations / max(1, base["iterations"]), 3)}
+    log("C2 deflation: %s" % rec)
+    del defl, V
+    return rec
 
 
 def _event_time(fn, reps):

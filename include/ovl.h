@@ -382,7 +382,8 @@ int ovl_host_heev(int n, const double* A, double* w, double* V);
 /* ovl_overlap_eigs: eigenpairs of the massless overlap operator
  *   D = 1 + gamma5 sign(H_w) (eq. 3) closest to zero, computed in one chiral
  *   sector as the paper does (Sec. V): thick-restart Lanczos (FP64, full
- *   re-orthogonalisation, basis of K <= 512 vectors) on the Hermitian
+ *   re-orthogonalisation, basis of K <= 512 chiral half-vectors, 6 complex
+ *   per site) on the Hermitian
  *   K_s = s P_s sign(H_w) P_s, P_s = (1 + s gamma5)/2, s = sector (+1 or -1),
  *   each matvec one sign application with `sign` and `lowmodes`.  The ell
  *   lowest eigenvectors v (eigenvalue k) of K_s give, with
@@ -397,7 +398,7 @@ int ovl_host_heev(int n, const double* A, double* w, double* V);
  *   sector vectors are <= tol or after max_iter restart cycles
  *   (OVL_W_NOT_CONVERGED); stats->max_residual is the recomputed
  *   ||K_s v - k v||, stats->hw_applies counts D_w applications.  Device
- *   workspace: K + 3 FP64 spinors.
+ *   workspace: (K + 2)/2 + 3 FP64 spinors.
  * ovl_deflation_create: n eigenpairs (xi_i, d_i) of D for the deflated CG
  *   (ovl_solve_opts.deflation, eq. 9).  Xi: n orthonormal FP64 spinors,
  *   caller-owned device memory BORROWED for the handle's lifetime; d: host

@@ -16,7 +16,11 @@
 // re-orthogonalisation, each matvec one sign application of the polynomial
 // approximation with the low modes of H_w projected exactly, eq. 7), Ritz
 // residuals from the Lanczos relation, the final ones recomputed from the
-// same sign application that gives u.
+// same sign application that gives u.  The basis is kept as chiral
+// half-vectors (the 6 components of chirality s per site), half the memory
+// and half the re-orthogonalisation traffic of full spinors; a matvec
+// expands its input into a full vector, applies the sign, and keeps the
+// sector rows of the result.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -53,6 +57,34 @@ struct DevBuf {
 
 char* vat(void* base, size_t v64, int i) { return static_cast<char*>(base) + static_cast<size_t>(i) * v64; }
 
+// Chiral half-vectors (Sec. V: a vector of definite chirality needs half the
+// storage).  A half-vector of sector s holds the 6 complex components of
+// chirality s per site, [parity][6][N/2] FP64 elements of 16 bytes: the rows
+// c = 0..5 (s = +1) or 6..11 (s = -1) of the full layout [parity][12][N/2].
+// The basis kernels (dots, axpys, rotations) treat a vector as a flat array
+// of 16-byte elements, so a half-vector goes to them as a full vector on a
+// geometry of N/2 sites (N/2 is a multiple of 8 on every valid lattice).
+ovl_geom half_geom(const ovl_geom* g) {
+  ovl_geom h = *g;
+  h.N = g->N / 2;
+  h.geo.Nh = g->geo.Nh / 2;
+  return h;
+}
+
+// half <- the sector rows of the full FP64 vector f (that is, P_s f)
+void to_half(void* h, const void* f, const ovl_geom* g, int sector, hipStream_t s) {
+  const size_t row = static_cast<size_t>(g->geo.Nh) * 16, c0 = sector > 0 ? 0 : 6;
+  OVL_HIP(hipMemcpy2DAsync(h, 6 * row, static_cast<const char*>(f) + c0 * row, 12 * row, 6 * row, 2,
+                           hipMemcpyDeviceToDevice, s));
+}
+
+// the sector rows of the full FP64 vector f <- half (the other rows untouched)
+void to_full(void* f, const void* h, const ovl_geom* g, int sector, hipStream_t s) {
+  const size_t row = static_cast<size_t>(g->geo.Nh) * 16, c0 = sector > 0 ? 0 : 6;
+  OVL_HIP(hipMemcpy2DAsync(static_cast<char*>(f) + c0 * row, 12 * row, h, 6 * row, 6 * row, 2,
+                           hipMemcpyDeviceToDevice, s));
+}
+
 }  // namespace
 }  // namespace ovl
 
@@ -73,12 +105,13 @@ int ovl_overlap_eigs(const ovl_gauge* u, double rho, const ovl_sign* sgn, const 
     const auto t0 = std::chrono::steady_clock::now();
     hipStream_t s = static_cast<hipStream_t>(st);
     const ovl_geom* g = &u->geom;
-    const size_t v64 = spinor_vec_bytes(g, OVL_F64);
+    const ovl_geom hg = half_geom(g);  // the Lanczos basis: chiral half-vectors
+    const size_t v64 = spinor_vec_bytes(g, OVL_F64), vh = v64 / 2;
     const size_t N = static_cast<size_t>(g->N);
     *stats = ovl_eig_stats{};
     const int keep = std::max(ell + 4, std::min(K - 4, ell + (K - ell) / 2));  // thick-restart size
 
-    DevBuf Q(v64 * (K + 1)), w(v64), t(v64);
+    DevBuf Q(vh * (K + 1)), w(vh), t(v64), xf(v64), wf(v64);
     DevBuf sc(sizeof(double) * 4 + sizeof(int) * 2);
     double* dsc = static_cast<double*>(sc.p);
     int* dsect = reinterpret_cast<int*>(dsc + 4);
@@ -86,31 +119,35 @@ int ovl_overlap_eigs(const ovl_gauge* u, double rho, const ovl_sign* sgn, const 
     DevBuf Sdev(sizeof(double2) * static_cast<size_t>(K) * K);
     const int hsect[2] = {sector, -sector};
     OVL_HIP(hipMemcpyAsync(dsect, hsect, sizeof(hsect), hipMemcpyHostToDevice, s));
+    blas_zero(xf.p, v64, s);  // the rows of chirality -s stay zero
 
-    auto norm = [&](const void* x) {
-      blas_norm2(OVL_F64, v64 / 16, x, 1, v64, dsc, s);
+    // norm of a vector of `bytes` bytes
+    auto norm = [&](const void* x, size_t bytes) {
+      blas_norm2(OVL_F64, bytes / 16, x, 1, bytes, dsc, s);
       double h[2];
       OVL_HIP(hipMemcpyAsync(h, dsc, sizeof(h), hipMemcpyDeviceToHost, s));
       OVL_HIP(hipStreamSynchronize(s));
       return std::sqrt(h[0]);
     };
-    // y = a x (+ b y), complex host scalars
-    auto axpby = [&](const void* x, zc a, void* y, bool keep_y, zc b = zc(1.0, 0.0)) {
+    // y = a x (+ b y) on vectors of `sites` sites' worth of FP64 elements,
+    // complex host scalars
+    auto axpby = [&](size_t sites, const void* x, zc a, void* y, bool keep_y, zc b = zc(1.0, 0.0)) {
       const double h[4] = {a.real(), a.imag(), b.real(), b.imag()};
       OVL_HIP(hipMemcpyAsync(dsc, h, sizeof(h), hipMemcpyHostToDevice, s));
-      blas_axpby(OVL_F64, x, dsc, OVL_F64, y, keep_y ? dsc + 2 : nullptr, N, 1, s);
+      blas_axpby(OVL_F64, x, dsc, OVL_F64, y, keep_y ? dsc + 2 : nullptr, sites, 1, s);
       OVL_HIP(hipStreamSynchronize(s));  // the host scalars are reused
     };
-    // out = eps in (FP64), counted
+    // out = eps in (FP64, full vectors), counted
     auto eps = [&](void* out, const void* in) {
       overlap_apply(out, in, u, rho, 0.0, sgn, lm, 0, OVL_F64, 1, s);
       stats->hw_applies += 2 * (static_cast<int64_t>(sgn->c.size()) - 1) + 1;
     };
-    // out = K_s in = s P_s eps in
+    // out = K_s in = s P_s eps in, on half-vectors
     auto apply_K = [&](void* out, const void* in) {
-      eps(t.p, in);
-      blas_chiral(OVL_F64, v64, t.p, 1, dsect, s);
-      axpby(t.p, zc(sector, 0.0), out, false);
+      to_full(xf.p, in, g, sector, s);
+      eps(t.p, xf.p);
+      to_half(out, t.p, g, sector, s);
+      if (sector < 0) axpby(N / 2, out, zc(-1.0, 0.0), out, false);
     };
     auto upload_S = [&](const std::vector<zc>& S, int rows, int cols) {
       std::vector<double2> h(static_cast<size_t>(rows) * cols);
@@ -119,13 +156,12 @@ int ovl_overlap_eigs(const ovl_gauge* u, double rho, const ovl_sign* sgn, const 
       OVL_HIP(hipStreamSynchronize(s));
     };
 
-    // q_0: the caller's start vector, projected to the sector
-    OVL_HIP(hipMemcpyAsync(Q.p, V, v64, hipMemcpyDeviceToDevice, s));
-    blas_chiral(OVL_F64, v64, Q.p, 1, dsect, s);
+    // q_0: the sector part of the caller's start vector
+    to_half(Q.p, V, g, sector, s);
     {
-      const double n0 = norm(Q.p);
+      const double n0 = norm(Q.p, vh);
       OVL_REQUIRE(n0 > 0.0 && std::isfinite(n0), OVL_E_ARG, "start vector has no component in the sector");
-      axpby(Q.p, zc(1.0 / n0, 0.0), Q.p, false);
+      axpby(N / 2, Q.p, zc(1.0 / n0, 0.0), Q.p, false);
     }
     std::vector<zc> T(static_cast<size_t>(K + 1) * (K + 1), zc(0.0, 0.0));
     auto Tat = [&](int i, int j) -> zc& { return T[i + static_cast<size_t>(K + 1) * j]; };
@@ -136,10 +172,10 @@ int ovl_overlap_eigs(const ovl_gauge* u, double rho, const ovl_sign* sgn, const 
     double worst = INFINITY;
     for (int cycle = 0;; ++cycle) {
       for (int j = cur; j < K; ++j) {
-        apply_K(w.p, vat(Q.p, v64, j));
+        apply_K(w.p, vat(Q.p, vh, j));
         for (int i = 0; i <= j; ++i) hc2[i] = make_double2(0.0, 0.0);
         for (int pass = 0; pass < 2; ++pass) {  // w -= Q (Q^dag w), twice
-          block_dot(g, Q.p, j + 1, w.p, OVL_F64, 1, static_cast<double2*>(cb.p), s);
+          block_dot(&hg, Q.p, j + 1, w.p, OVL_F64, 1, static_cast<double2*>(cb.p), s);
           OVL_HIP(hipMemcpyAsync(hc.data(), cb.p, sizeof(double2) * (j + 1), hipMemcpyDeviceToHost, s));
           OVL_HIP(hipStreamSynchronize(s));
           for (int i = 0; i <= j; ++i) {
@@ -147,15 +183,15 @@ int ovl_overlap_eigs(const ovl_gauge* u, double rho, const ovl_sign* sgn, const 
             hc[i] = make_double2(-hc[i].x, -hc[i].y);
           }
           OVL_HIP(hipMemcpyAsync(cb.p, hc.data(), sizeof(double2) * (j + 1), hipMemcpyHostToDevice, s));
-          block_axpy(g, Q.p, j + 1, static_cast<const double2*>(cb.p), w.p, OVL_F64, 1, true, s);
+          block_axpy(&hg, Q.p, j + 1, static_cast<const double2*>(cb.p), w.p, OVL_F64, 1, true, s);
           OVL_HIP(hipStreamSynchronize(s));
         }
         for (int i = 0; i <= j; ++i) Tat(i, j) = zc(hc2[i].x, hc2[i].y);
-        const double beta = norm(w.p);
+        const double beta = norm(w.p, vh);
         OVL_REQUIRE(std::isfinite(beta), OVL_E_NAN, "overlap eigensolver: NaN in the Lanczos recurrence");
         if (beta == 0.0) throw Error(OVL_E_BREAKDOWN, "overlap eigensolver: invariant subspace found before K steps");
         Tat(j + 1, j) = beta;
-        axpby(w.p, zc(1.0 / beta, 0.0), vat(Q.p, v64, j + 1), false);
+        axpby(N / 2, w.p, zc(1.0 / beta, 0.0), vat(Q.p, vh, j + 1), false);
       }
       // Ritz pairs, lowest first; residual ||K y - theta y|| = beta_K |s_{K-1}|
       std::vector<zc> Tk(static_cast<size_t>(K) * K);
@@ -172,8 +208,8 @@ int ovl_overlap_eigs(const ovl_gauge* u, double rho, const ovl_sign* sgn, const 
       if (worst <= tol || cycle + 1 >= max_iter) break;
       // thick restart: the `keep` lowest Ritz vectors and the residual direction
       upload_S(S, K, K);
-      block_rotate_inplace(g, Q.p, K, static_cast<const double2*>(Sdev.p), keep, s);
-      OVL_HIP(hipMemcpyAsync(vat(Q.p, v64, keep), vat(Q.p, v64, K), v64, hipMemcpyDeviceToDevice, s));
+      block_rotate_inplace(&hg, Q.p, K, static_cast<const double2*>(Sdev.p), keep, s);
+      OVL_HIP(hipMemcpyAsync(vat(Q.p, vh, keep), vat(Q.p, vh, K), vh, hipMemcpyDeviceToDevice, s));
       std::fill(T.begin(), T.end(), zc(0.0, 0.0));
       for (int i = 0; i < keep; ++i) {
         Tat(i, i) = th[i];
@@ -186,24 +222,24 @@ int ovl_overlap_eigs(const ovl_gauge* u, double rho, const ovl_sign* sgn, const 
     // the ell lowest Ritz vectors, then the pairs of D from each of them;
     // vector i of the sector sits in Q[i] after the rotation
     upload_S(S, K, K);
-    block_rotate_inplace(g, Q.p, K, static_cast<const double2*>(Sdev.p), ell, s);
+    block_rotate_inplace(&hg, Q.p, K, static_cast<const double2*>(Sdev.p), ell, s);
     int n = 0;
     double max_res = 0.0;
     const double r2 = 1.0 / std::sqrt(2.0);
     for (int i = 0; i < ell; ++i) {
-      void* v = vat(Q.p, v64, i);
-      eps(t.p, v);
-      // w = P_{-s} eps v (the partner direction), t = P_s eps v
-      OVL_HIP(hipMemcpyAsync(w.p, t.p, v64, hipMemcpyDeviceToDevice, s));
-      blas_chiral(OVL_F64, v64, w.p, 1, dsect + 1, s);
+      to_full(xf.p, vat(Q.p, vh, i), g, sector, s);  // v as a full vector
+      eps(t.p, xf.p);
+      // wf = P_{-s} eps v (the partner direction), t = P_s eps v
+      OVL_HIP(hipMemcpyAsync(wf.p, t.p, v64, hipMemcpyDeviceToDevice, s));
+      blas_chiral(OVL_F64, v64, wf.p, 1, dsect + 1, s);
       blas_chiral(OVL_F64, v64, t.p, 1, dsect, s);
       // explicit residual ||s P_s eps v - k v||
-      axpby(v, zc(-sector * th[i], 0.0), t.p, true);
-      max_res = std::max(max_res, norm(t.p));
-      const double sn = norm(w.p);
+      axpby(N, xf.p, zc(-sector * th[i], 0.0), t.p, true);
+      max_res = std::max(max_res, norm(t.p, v64));
+      const double sn = norm(wf.p, v64);
       const double k = std::min(1.0, std::max(-1.0, th[i]));
       if (sn <= 1e-9) {  // real mode of chirality `sector`
-        OVL_HIP(hipMemcpyAsync(vat(V, v64, n), v, v64, hipMemcpyDeviceToDevice, s));
+        OVL_HIP(hipMemcpyAsync(vat(V, v64, n), xf.p, v64, hipMemcpyDeviceToDevice, s));
         d[2 * n] = 1.0 + k;
         d[2 * n + 1] = 0.0;
         ++n;
@@ -213,8 +249,8 @@ int ovl_overlap_eigs(const ovl_gauge* u, double rho, const ovl_sign* sgn, const 
       for (int half = 0; half < 2; ++half) {
         const int sg = (half == 0) ? -sector : sector;
         void* xo = vat(V, v64, n);
-        axpby(v, zc(r2, 0.0), xo, false);
-        axpby(w.p, zc(0.0, sg * r2 / sn), xo, true);
+        axpby(N, xf.p, zc(r2, 0.0), xo, false);
+        axpby(N, wf.p, zc(0.0, sg * r2 / sn), xo, true);
         d[2 * n] = 1.0 + k;
         d[2 * n + 1] = sg * sector * sn;
         ++n;
