@@ -457,9 +457,13 @@ int ovl_net_apply(const ovl_net* n, const ovl_gauge* u, const void* in, void* ou
  *   nrhs/KR groups side by side in one workgroup (32 or 64 sites x groups
  *   threads, at most 512); (c) one-vector kernels that issue the loads of
  *   the next 1..3 directions before the arithmetic of the current one
- *   (pipeline depth 2..4); each in h order or in t-major order (blocks of a
+ *   (pipeline depth 2..4); each in h order, in t-major order (blocks of a
  *   parity walk t for a fixed tile of the x-y-z half slice, so that
- *   t-neighbours come from cache).
+ *   t-neighbours come from cache) or in z-slab order (blocks cover a slab
+ *   of tm = 4 or 8 z-planes at t, then the same slab at t + 1, ..., so a
+ *   site's t-neighbours are read a slab apart instead of a whole 3-d slice;
+ *   the last slab may be thinner).  shape[4] = tm: 0 h order, 1 t-major,
+ *   2..Lz slab thickness.
  * ovl_stencil_shape: shape[5] = {kr, bs, pipe, rin, tm} tuned for a
  *   full-lattice configuration (precision, link compression, number of
  *   extra epilogue vectors 0..3, batch size); all 0 when it has not been

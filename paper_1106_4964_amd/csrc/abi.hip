@@ -140,7 +140,7 @@ int ovl_stencil_set_shape(const ovl_geom* g, ovl_prec prec, int compress12, int 
     OVL_REQUIRE(nextra >= 0 && nextra <= 3, OVL_E_ARG, "nextra must be 0..3");
     OVL_REQUIRE(bs == 32 || bs == 64 || bs == 128 || bs == 256, OVL_E_ARG, "bs must be 32, 64, 128 or 256");
     OVL_REQUIRE(rin == 0 || rin == 1, OVL_E_ARG, "rin must be 0 or 1");
-    OVL_REQUIRE(tm == 0 || tm == 1, OVL_E_ARG, "tm must be 0 or 1");
+    OVL_REQUIRE(tm >= 0 && tm <= g->dims[2], OVL_E_ARG, "tm must be 0, 1 or a slab thickness <= Lz");
     if (pipe) {
       OVL_REQUIRE(kr == 1 && rin == 0 && pipe >= 2 && pipe <= 4, OVL_E_ARG,
                   "pipelined shapes need kr = 1, rin = 0, depth 2..4");

@@ -49,10 +49,12 @@ bool tuning_enabled() {
   return m == 1;
 }
 
-std::vector<Shape> candidates(int prec, int nrhs) {
+std::vector<Shape> candidates(int prec, int nrhs, int Lz) {
   std::vector<Shape> c;
   const int kmax = prec == OVL_F64 ? 2 : 4;
-  for (int tm = 0; tm <= 1; ++tm) {
+  // block orders: by h, t-major, and z-slabs of 4 and 8 planes
+  for (int tm : {0, 1, 4, 8}) {
+    if (tm > Lz) continue;
     for (int kr = 1; kr <= kmax; ++kr)
       if (nrhs % kr == 0) {
         for (int bs : {128, 256}) c.push_back({kr, bs, 0, 0, tm});
@@ -96,7 +98,7 @@ Shape pick_shape(const StencilArgs& A, int prec, int recon, int nrhs, hipStream_
   // warm-up launch; a candidate's time is its better round.  The first
   // candidate (in list order) within 2% of the fastest wins, so that shapes
   // that time alike give the same choice from run to run.
-  const std::vector<Shape> cand = candidates(prec, nrhs);
+  const std::vector<Shape> cand = candidates(prec, nrhs, A.g.Lz);
   std::vector<float> best_ms(cand.size(), 1e30f);
   for (int round = 0; round < 2; ++round)
     for (size_t i = 0; i < cand.size(); ++i) {

@@ -26,7 +26,8 @@ struct StencilArgs {
   int par0, npar;
   size_t vstride;
   // 1: consecutive blocks of a parity walk t at a fixed tile of the (x, y, z)
-  // half-slice, so t-neighbours are reused from cache; 0: blocks follow h
+  // half-slice, so t-neighbours are reused from cache; Z >= 2: blocks walk t
+  // over a slab of Z z-planes before the next slab; 0: blocks follow h
   int tmaj = 0;
 };
 

@@ -23,7 +23,7 @@ struct Shape {
   int bs;    // threads per block (sites per block when rin)
   int pipe;  // 0: plain kernel; >= 2: pipelined one-vector kernel of that depth
   int rin;   // 1: the nrhs/kr vector groups are the y-dimension of the block
-  int tm;    // 1: t-major block order (StencilArgs::tmaj)
+  int tm;    // block order (StencilArgs::tmaj): 0 by h, 1 t-major, >= 2 z-slabs of tm planes
 };
 
 // Launches the stencil in shape sh for one storage precision (one function
@@ -353,6 +353,21 @@ __device__ inline bool stencil_site(const StencilArgs& A, int& p, int& h) {
     p = A.par0;
     hb = lb;
   }
+  if (A.tmaj >= 2) {
+    // z-slabs of Z = tmaj planes: consecutive blocks cover one slab's
+    // (x, y, z) half-slice at t, then the same slab at t + 1, ..., before the
+    // next slab, so a site's t-neighbours are read 2 Z Lx Ly / 2 half-sites
+    // apart in launch order instead of Lx Ly Lz (a slice of the whole lattice)
+    const int Z = A.tmaj, bps = (Z * A.g.sz + static_cast<int>(blockDim.x) - 1) / static_cast<int>(blockDim.x);
+    const int per_slab = bps * A.g.Lt;
+    const int slab = hb / per_slab, r = hb - slab * per_slab;
+    const int t = r / bps, j = r - t * bps;
+    const int z0 = slab * Z;
+    const int len = min(Z, A.g.Lz - z0) * A.g.sz;  // the last slab may be thinner
+    const int hl = j * static_cast<int>(blockDim.x) + static_cast<int>(threadIdx.x);
+    h = t * A.g.st + z0 * A.g.sz + hl;
+    return hl < len;
+  }
   if (A.tmaj) {
     const int tile = hb / A.g.Lt, t = hb - tile * A.g.Lt;
     const int hl = tile * blockDim.x + threadIdx.x;
@@ -494,7 +509,15 @@ template <int P, int R, int NV>
 void launch_k(const StencilArgs& A0, int nrhs, Shape sh, hipStream_t s) {
   StencilArgs A = A0;
   A.tmaj = sh.tm;
-  const int hblocks = sh.tm ? ((A.g.st + sh.bs - 1) / sh.bs) * A.g.Lt : (A.g.Nh + sh.bs - 1) / sh.bs;
+  int hblocks;
+  if (sh.tm >= 2) {
+    OVL_REQUIRE(sh.tm <= A.g.Lz, OVL_E_ARG, "stencil: slab thicker than the lattice");
+    hblocks = ((A.g.Lz + sh.tm - 1) / sh.tm) * A.g.Lt * ((sh.tm * A.g.sz + sh.bs - 1) / sh.bs);
+  } else if (sh.tm == 1) {
+    hblocks = ((A.g.st + sh.bs - 1) / sh.bs) * A.g.Lt;
+  } else {
+    hblocks = (A.g.Nh + sh.bs - 1) / sh.bs;
+  }
   if (sh.rin) {
     const int groups = nrhs / sh.kr;
     OVL_REQUIRE(sh.bs * groups <= 512, OVL_E_ARG, "stencil: block too large");

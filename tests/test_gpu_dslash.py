@@ -175,7 +175,9 @@ def test_every_vectors_per_thread_shape(prec):
 def _shape_candidates(prec, nrhs):
     kmax = 2 if prec == ovl.OVL_F64 else 4
     out = []
-    for tm in (0, 1):
+    # block orders: by h, t-major, z-slabs of 2, 4 (ragged last slab on
+    # Lz = 6), 5 (ragged) and 6 planes
+    for tm in (0, 1, 2, 4, 5, 6):
         for kr in range(1, kmax + 1):
             if nrhs % kr:
                 continue
@@ -212,9 +214,9 @@ def test_every_pinned_shape(prec):
             got = gu.unpack(g, out, prec, 12)
             assert gu.max_rel_err(got, want) <= 2 * gu.UNIT_ROUNDOFF[prec], shape
         # unsupported block size, kr, block above 512 threads, pipelined kr > 1,
-        # pipeline depth, rin flag, tm flag
+        # pipeline depth, rin flag, slab thicker than Lz = 6
         for bad in [(1, 96, 0, 0, 0), (5, 128, 0, 0, 0), (1, 64, 0, 1, 0), (2, 128, 2, 0, 0), (1, 128, 5, 0, 0),
-                    (1, 128, 0, 2, 0), (1, 128, 0, 0, 2)]:
+                    (1, 128, 0, 2, 0), (1, 128, 0, 0, 7)]:
             with pytest.raises(ovl.OvlError):
                 ovl.stencil_set_shape(g, prec, c12, 0, 12, bad)
     finally:
