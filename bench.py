@@ -278,8 +278,9 @@ def spectral_setup(ovl, g, gauge, dims, rho, ell, delta, seed_base, tol=1e-12):
 # ---------------------------------------------------------------------------
 def learned_mode(args, dims):
     """The learned preconditioner at scale: a 1-4-1 PTC network trained on
-    (b, x) pairs from four 16^3x32 fields, then the right preconditioner of
-    FGCR for D(m) on the 24^3x64 field, against mixed CG and FGCR with M = 1."""
+    (b, x) pairs harvested from plain CG solves on four 16^3x32 fields, then
+    the right preconditioner of the batched FGCR for D(m) on the 24^3x64
+    field, against mixed CG and FGCR with M = 1."""
     import numpy as np
     import torch
 
@@ -296,21 +297,35 @@ def learned_mode(args, dims):
     vb = tg.spinor_bytes(F32)
     fields = []
     t0 = time.perf_counter()
+    harvest = []
     for seed in (41, 42, 43, 44):
         log("training field %s seed %d" % (tdims, seed))
         gt = ovl.Gauge(tg, torch.from_numpy(si.gauge_field(tdims, 0.25, seed)).to(dev))
         gt.set_repr(F32, 0)
-        _, _, Vt, lmt, st_ = spectral_setup(ovl, tg, gt, tdims, rho, 20, 1e-8, 100 * seed, tol=1e-10)
+        _, lams_t, Vt, lmt, st_ = spectral_setup(ovl, tg, gt, tdims, rho, 20, 1e-8, 100 * seed, tol=1e-10)
+        sin_t = ovl.Sign(abs(lams_t[-1]), st_.lam_max, delta=args.inner_delta)
+        # (b, x) pairs from plain CG: the FP32 search directions p of the
+        # inner iterations and their images b = D(m) p, every 8th iteration,
+        # from batches of 12 Gaussian sources until the buffers are full
         X = torch.empty(tg.spinor_bytes(F32, pairs_per_field), dtype=torch.uint8, device=dev)
         B = torch.empty_like(X)
-        tmp = torch.empty(tg.spinor_bytes(F64, 12), dtype=torch.uint8, device=dev)
-        for i0 in range(0, pairs_per_field, 12):
-            k = min(12, pairs_per_field - i0)
-            blk = np.stack([si.gaussian_spinor(tdims, 10000 * seed + i0 + j) for j in range(k)])
-            ovl.ovl_pack_spinor(tg, torch.from_numpy(blk).to(dev), tmp, F64, k, None)
-            ovl.ovl_convert(tg, tmp, F64, X[i0 * vb:], F32, k, None)
-            ovl.ovl_overlap_apply(B[i0 * vb:], X[i0 * vb:], gt, rho, mass, st_, lmt, 0, F32, k, None)
+        got, batch, cg_its = 0, 0, 0
+        while got < pairs_per_field:
+            blk = np.stack([si.gaussian_spinor(tdims, 10000 * seed + 12 * batch + j) for j in range(12)])
+            b64t = torch.empty(tg.spinor_bytes(F64, 12), dtype=torch.uint8, device=dev)
+            ovl.ovl_pack_spinor(tg, torch.from_numpy(blk).to(dev), b64t, F64, 12, None)
+            xt = torch.zeros_like(b64t)
+            opts = ovl.SolveOpts(F32, 1e-5, 0, 1, 60, X[got * vb:].data_ptr(), B[got * vb:].data_ptr(),
+                                 pairs_per_field - got, sin_t.handle.value)
+            opts.harvest_stride = 8
+            stt = ovl.SolveStats()
+            ovl.ovl_cg_solve(xt, b64t, 12, gt, rho, mass, st_, lmt, 1e-8, 20000, opts, ctypes.byref(stt), None)
+            got += stt.harvested
+            cg_its += stt.iterations
+            batch += 1
         torch.cuda.synchronize()
+        harvest.append({"seed": seed, "pairs": got, "cg_batches": batch, "cg_iterations": cg_its})
+        log("harvested %d pairs from %d CG solves of 12 sources (%d iterations)" % (got, batch, cg_its))
         fields.append((gt, X, B, Vt, lmt, st_))
     t_pairs = time.perf_counter() - t0
     net_t = ovl.Net(tg, 4)
@@ -373,7 +388,8 @@ def learned_mode(args, dims):
                                "FGCR restart %d; net 1-4-1 trained on %d pairs from four %s fields"
                                % (mass, args.prec, args.ell, args.delta, args.inner_delta, args.restart, args.pairs,
                                   "x".join(map(str, tdims)))},
-        "training": {"seconds_pairs": round(t_pairs, 1), "seconds_train": round(t_train, 1), "loss": losses},
+        "training": {"seconds_pairs": round(t_pairs, 1), "seconds_train": round(t_train, 1), "loss": losses,
+                     "harvest": harvest},
         "solves": out,
     }
     print(json.dumps(res), flush=True)

@@ -291,6 +291,9 @@ typedef struct {
   const ovl_deflation* deflation; /* CG only: eigenpairs of D deflated in
                                      every defect-correction cycle (eq. 9);
                                      NULL = none.  Not with chiral.       */
+  int harvest_stride;  /* harvest the pairs of every stride-th inner
+                          iteration (<= 1: every one), so a capped harvest
+                          spans the whole solve                           */
 } ovl_solve_opts;
 
 typedef struct {
@@ -315,7 +318,10 @@ int ovl_cg_solve(void* x, const void* b, int nrhs, const ovl_gauge* u, double rh
  *   (needs the FP32 link representation).  M = NULL gives plain GCR.  If a
  *   cycle reduces the residual by less than a factor 0.9, or an iterate is
  *   not finite, the solve is finished by ovl_cg_solve from the current x and
- *   stats->fallback_used is set.  Bases: 2*restart*nrhs FP64 spinors.
+ *   stats->fallback_used is set.  The rhs run in lockstep (one batched M,
+ *   D(m), orthogonalisation and update per iteration, scalars on the
+ *   device); a converged rhs is frozen while the others go on.  Bases:
+ *   2*restart*nrhs FP64 spinors.
  */
 int ovl_fgcr_solve(void* x, const void* b, int nrhs, const ovl_gauge* u, double rho, double m, const ovl_sign* sign,
                    const ovl_lowmodes* lowmodes, const ovl_net* M, int restart, double tol, int maxiter,

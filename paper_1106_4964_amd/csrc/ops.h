@@ -114,7 +114,7 @@ int cg_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, doub
              hipStream_t us);
 
 // out = M in for one FP32 spinor (learned preconditioner).
-void net_apply(const ovl_net* net, const ovl_gauge* u, const void* in, void* out, hipStream_t s);
+void net_apply(const ovl_net* net, const ovl_gauge* u, const void* in, void* out, int nrhs, hipStream_t s);
 
 // Counters of stencil work issued from the host (not counting graph replays).
 void count_stencil(int nrhs);

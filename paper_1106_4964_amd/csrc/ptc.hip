@@ -68,10 +68,15 @@ __device__ inline void transport(const Geo& g, const void* links, const char* f,
 }
 
 // out[a] = sum_b sum_k W[k][a][b] T_k in[b]; W in LDS as float2 [k][a][b][s][t].
+// blockIdx.y selects one field of a batch: its channels start rstride_in
+// (rstride_out) bytes after the previous field's.
 template <int R>
 __global__ __launch_bounds__(256) void ptc_forward_kernel(Geo g, const void* links, const char* in, char* out,
-                                                          size_t vstride, int cin, int cout, const float2* W) {
+                                                          size_t vstride, int cin, int cout, const float2* W,
+                                                          size_t rstride_in, size_t rstride_out) {
   __shared__ float2 w[NPATH * CMAX * CMAX * 16];
+  in += blockIdx.y * rstride_in;
+  out += blockIdx.y * rstride_out;
   const int nw = NPATH * cin * cout * 16;
   for (int i = threadIdx.x; i < nw; i += blockDim.x) w[i] = W[i];
   __syncthreads();
@@ -229,15 +234,17 @@ struct Layer {
   hipStream_t s;
   size_t vstride;
 
-  void forward(const void* in, void* out, int cin, int cout, const float2* W) const {
+  // nb fields at once: field f reads in + f cin vstride, writes out + f cout vstride
+  void forward(const void* in, void* out, int cin, int cout, const float2* W, int nb = 1) const {
     const Geo& g = u->geom.geo;
-    dim3 grid((2 * g.Nh + 255) / 256);
+    dim3 grid((2 * g.Nh + 255) / 256, nb);
+    const size_t ri = vstride * cin, ro = vstride * cout;
     if (recon == 18)
       hipLaunchKernelGGL(ptc_forward_kernel<18>, grid, dim3(256), 0, s, g, links, static_cast<const char*>(in),
-                         static_cast<char*>(out), vstride, cin, cout, W);
+                         static_cast<char*>(out), vstride, cin, cout, W, ri, ro);
     else
       hipLaunchKernelGGL(ptc_forward_kernel<12>, grid, dim3(256), 0, s, g, links, static_cast<const char*>(in),
-                         static_cast<char*>(out), vstride, cin, cout, W);
+                         static_cast<char*>(out), vstride, cin, cout, W, ri, ro);
     OVL_HIP(hipGetLastError());
   }
   void wgrad(const void* in, const void* gout, int cin, int cout, double2* out, int accumulate = 0) const {
@@ -268,16 +275,17 @@ Layer make_layer(const ovl_gauge* u, hipStream_t s) {
 
 }  // namespace
 
-// out = M in for one FP32 field (in, out: FP32 spinors); hidden buffer from the pool.
-void net_apply(const ovl_net* net, const ovl_gauge* u, const void* in, void* out, hipStream_t s) {
+// out_r = M in_r for a batch of nrhs FP32 fields (back to back); the hidden
+// channels of the batch come from the pool.
+void net_apply(const ovl_net* net, const ovl_gauge* u, const void* in, void* out, int nrhs, hipStream_t s) {
   Layer L = make_layer(u, s);
   const int C = net->hidden;
-  WsBuf hid(L.vstride * C, s);
+  WsBuf hid(L.vstride * C * nrhs, s);
   WsBuf w1(net->w1.size() * sizeof(float2), s), w2(net->w2.size() * sizeof(float2), s);
   upload(net->w1, static_cast<float2*>(w1.p), s);
   upload(net->w2, static_cast<float2*>(w2.p), s);
-  L.forward(in, hid.p, 1, C, static_cast<const float2*>(w1.p));
-  L.forward(hid.p, out, C, 1, static_cast<const float2*>(w2.p));
+  L.forward(in, hid.p, 1, C, static_cast<const float2*>(w1.p), nrhs);
+  L.forward(hid.p, out, C, 1, static_cast<const float2*>(w2.p), nrhs);
 }
 
 }  // namespace ovl
@@ -466,7 +474,7 @@ int ovl_net_apply(const ovl_net* n, const ovl_gauge* u, const void* in, void* ou
   return guard([&] {
     OVL_REQUIRE(n && u && in && out, OVL_E_ARG, "null argument");
     OVL_REQUIRE(in != out, OVL_E_ALIAS, "output must not alias the input");
-    net_apply(n, u, in, out, static_cast<hipStream_t>(st));
+    net_apply(n, u, in, out, 1, static_cast<hipStream_t>(st));
     return OVL_OK;
   });
 }

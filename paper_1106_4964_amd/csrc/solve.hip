@@ -236,13 +236,15 @@ int cg_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, doub
       }
     };
 
+    const int hstride = std::max(1, opt.harvest_stride);
+    int hv_it = 0;
     // inner-iteration body; records nothing but kernel launches
     auto body = [&]() {
       S.norm2(p.p, P, dS->pp, dS);
       hipLaunchKernelGGL(alpha_kernel, dim3(1), dim3(64), 0, s, R, dS);
       blas_axpby(P, p.p, dS->alpha, OVL_F64, e64.p, dS->one, S.nsites, R, s);
       S.dm(q.p, p.p, P, 0, true);
-      if (harvest && !capturing) harvest_pairs();
+      if (harvest && !capturing && hv_it++ % hstride == 0) harvest_pairs();
       blas_axpby(P, q.p, dS->malpha, P, rin.p, dS->one, S.nsites, R, s);
       S.norm2(rin.p, P, dS->rrn, dS);
       hipLaunchKernelGGL(beta_kernel, dim3(1), dim3(64), 0, s, R, dS);
@@ -443,9 +445,99 @@ int cg_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, doub
 
 // ------------------------------------------------------------------- FGCR
 // Flexible GCR with a right preconditioner M (the learned network, FP32) in
-// the FP64 defect-correction loop.  Each rhs keeps its own bases W (the
-// orthonormalised D(m) z) and Z (the matching search directions) in FP64;
-// the D(m) applications of a cycle run as one batch at the inner precision.
+// the FP64 defect-correction loop.  The rhs of the batch run in lockstep:
+// the bases W (the orthonormalised D(m) z) and Z (the matching search
+// directions) of all rhs sit in two FP64 blocks, vector (i, r) at index
+// i R + r, so one block_dot / block_axpy pair orthogonalises every rhs
+// against its own earlier directions (the cross-rhs coefficients are set to
+// zero on the device); M and D(m) run on the whole batch, and every Krylov
+// scalar stays on the device.  The host reads the per-rhs flags once per
+// iteration.
+namespace {
+
+// Device scalars of the batched GCR cycle, one slot per rhs.
+struct GcrScalars {
+  double rn2[OVL_MAX_RHS];           // ||r_r||^2 of the inner system
+  double target2[OVL_MAX_RHS];       // rhs r stops once rn2 <= target2
+  double tmp[2 * OVL_MAX_RHS];       // reduction output, (re, im) per rhs
+  double dot[2 * OVL_MAX_RHS];       // W_{j,r}^dag r_r
+  double alpha[2 * OVL_MAX_RHS];     // complex, 0 for inactive rhs
+  double malpha[2 * OVL_MAX_RHS];
+  double inv[2 * OVL_MAX_RHS];       // 1 / ||w_r|| (0 for inactive rhs)
+  double one[2 * OVL_MAX_RHS];
+  int active[OVL_MAX_RHS];
+  int bad[OVL_MAX_RHS];              // 1: w = 0 or not finite, 2: residual not finite
+};
+
+// K[(i R + v) R + r] = -C[(i R + v) R + r] if v == r and rhs r is active, else 0:
+// each rhs is projected on its own basis vectors only.
+__global__ void gcr_coef_kernel(int n, int R, const double2* C, double2* K, const GcrScalars* S) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int r = k % R, v = (k / R) % R;
+  const double2 c = C[k];
+  K[k] = (v == r && S->active[r]) ? make_double2(-c.x, -c.y) : make_double2(0.0, 0.0);
+}
+
+__global__ void gcr_norm_kernel(int R, GcrScalars* S) {
+  const int r = threadIdx.x;
+  if (r >= R) return;
+  double inv = 0.0;
+  if (S->active[r]) {
+    const double n2 = S->tmp[2 * r];
+    if (n2 > 0.0 && n2 <= 1.79e308) {
+      inv = 1.0 / sqrt(n2);
+    } else {
+      S->bad[r] = 1;
+      S->active[r] = 0;
+    }
+  }
+  S->inv[2 * r] = inv;
+  S->inv[2 * r + 1] = 0.0;
+}
+
+__global__ void gcr_alpha_kernel(int R, GcrScalars* S) {
+  const int r = threadIdx.x;
+  if (r >= R) return;
+  const bool a = S->active[r] != 0;
+  const double re = a ? S->dot[2 * r] : 0.0, im = a ? S->dot[2 * r + 1] : 0.0;
+  S->alpha[2 * r] = re;
+  S->alpha[2 * r + 1] = im;
+  S->malpha[2 * r] = -re;
+  S->malpha[2 * r + 1] = -im;
+}
+
+__global__ void gcr_check_kernel(int R, GcrScalars* S) {
+  const int r = threadIdx.x;
+  if (r >= R || !S->active[r]) return;
+  const double n2 = S->tmp[2 * r];
+  S->rn2[r] = n2;
+  if (!(n2 <= 1.79e308)) {
+    S->bad[r] = 2;
+    S->active[r] = 0;
+  } else if (n2 <= S->target2[r]) {
+    S->active[r] = 0;
+  }
+}
+
+// dst_r = active_r ? inv_r src_r : 0 over R FP64 vectors of n16 elements
+// (a select, so a non-finite src of an inactive rhs never reaches dst)
+__global__ void gcr_store_kernel(size_t n16, size_t vs, const double2* src, double2* dst, const GcrScalars* S) {
+  const int r = blockIdx.y;
+  const size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x;
+  if (i >= n16) return;
+  const size_t o = r * (vs / 16) + i;
+  if (S->active[r]) {
+    const double2 v = src[o];
+    const double a = S->inv[2 * r];
+    dst[o] = make_double2(a * v.x, a * v.y);
+  } else {
+    dst[o] = make_double2(0.0, 0.0);
+  }
+}
+
+}  // namespace
+
 int fgcr_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, double m, const ovl_sign* sg,
                const ovl_lowmodes* lm, const ovl_net* net, int restart, double tol, int maxiter,
                const ovl_solve_opts* o, ovl_solve_stats* st, hipStream_t us) {
@@ -481,7 +573,11 @@ int fgcr_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, do
     WsBuf zP(vP * R, s), wP(vP * R, s), w64(v64 * R, s), z64(v64 * R, s);
     WsBuf r32(net ? v32 * R : 16, s), z32(net ? v32 * R : 16, s);
     WsBuf Wb(v64 * R * restart, s), Zb(v64 * R * restart, s);
-    WsBuf sc(sizeof(double) * 4 * OVL_MAX_RHS, s), cb(sizeof(double2) * restart, s);
+    WsBuf sc(sizeof(double) * 4 * OVL_MAX_RHS, s);
+    WsBuf gsb(sizeof(GcrScalars), s);
+    WsBuf Cb(sizeof(double2) * static_cast<size_t>(restart) * R * R, s), Kb(sizeof(double2) * static_cast<size_t>(restart) * R * R, s);
+    GcrScalars* dG = static_cast<GcrScalars*>(gsb.p);
+    GcrScalars hG{};
     double* dsc = static_cast<double*>(sc.p);
     std::vector<double> bn2(R), rn2(R), h(4 * OVL_MAX_RHS);
     auto dev_scalars = [&](const std::vector<double>& v) {  // complex pairs -> dsc
@@ -500,29 +596,18 @@ int fgcr_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, do
       st->sign_applies += R;
       st->dslash_applies += R * (inner ? per_sign_dw_in : per_sign_dw);
     };
-    auto vec = [&](void* base, size_t vs, int i) { return static_cast<char*>(base) + static_cast<size_t>(i) * vs; };
-    // y_r += a x_r for one rhs (host scalar)
-    auto axpy1 = [&](const void* xx, void* yy, std::complex<double> a) {
-      std::vector<double> c = {a.real(), a.imag(), 1.0, 0.0};
-      dev_scalars(c);
-      blas_axpby(OVL_F64, xx, dsc, OVL_F64, yy, dsc + 2, N, 1, s);
-    };
-    auto dot1 = [&](const void* xx, const void* yy) {
-      blas_dot(OVL_F64, v64 / 16, xx, yy, 1, v64, dsc, s);
-      OVL_HIP(hipMemcpyAsync(h.data(), dsc, sizeof(double) * 2, hipMemcpyDeviceToHost, s));
-      OVL_HIP(hipStreamSynchronize(s));
-      return std::complex<double>(h[0], h[1]);
-    };
+    auto blk = [&](void* base, int j) { return static_cast<char*>(base) + static_cast<size_t>(j) * R * v64; };
+    const size_t n16 = v64 / 16;
+    const dim3 sgrid((n16 + 255) / 256, R);
 
     norms(b, R, v64, OVL_F64, bn2);
     for (int r = 0; r < R; ++r) OVL_REQUIRE(std::isfinite(bn2[r]), OVL_E_NAN, "right-hand side contains NaN or Inf");
     const double rms_target = P == OVL_F64 ? 1.0 : std::sqrt(12.0 * N) / 8.0;
     int its = 0;
     st->restarts = 0;
-    std::vector<double> ones(2 * OVL_MAX_RHS, 0.0), mones(2 * OVL_MAX_RHS, 0.0);
-    for (int r = 0; r < R; ++r) {
-      ones[2 * r] = 1.0;
-      mones[2 * r] = -1.0;
+    for (int r = 0; r < OVL_MAX_RHS; ++r) {
+      hG.one[2 * r] = 1.0;
+      hG.one[2 * r + 1] = 0.0;
     }
     for (;;) {
       dm(tmp64.p, x, OVL_F64, false);
@@ -556,30 +641,33 @@ int fgcr_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, do
       }
       ++st->restarts;
       // scaled inner system D e = r / scale
-      std::vector<double> scale(R), isc(2 * OVL_MAX_RHS, 0.0), target(R);
+      std::vector<double> scale(R), isc(2 * OVL_MAX_RHS, 0.0);
       for (int r = 0; r < R; ++r) {
         const double rn = std::sqrt(rn2[r]);
         scale[r] = active[r] ? rn / rms_target : 0.0;
         isc[2 * r] = active[r] ? 1.0 / scale[r] : 0.0;
         double rel = active[r] ? 0.5 * tol * std::sqrt(bn2[r]) / rn : 1.0;
         if (P != OVL_F64) rel = std::max(rel, inner_tol);
-        target[r] = std::min(rel, 1.0) * rms_target;
+        const double tg = std::min(rel, 1.0) * rms_target;
+        hG.target2[r] = tg * tg;
+        hG.rn2[r] = active[r] ? rms_target * rms_target : 0.0;
+        hG.active[r] = active[r];
+        hG.bad[r] = 0;
       }
       dev_scalars(isc);
       blas_axpby(OVL_F64, r64.p, dsc, OVL_F64, rin.p, nullptr, N, R, s);
       blas_zero(e64.p, v64 * R, s);
-      std::vector<double> rnorm(R);
-      for (int r = 0; r < R; ++r) rnorm[r] = active[r] ? rms_target : 0.0;
+      OVL_HIP(hipMemcpyAsync(dG, &hG, sizeof(GcrScalars), hipMemcpyHostToDevice, s));
       bool inner_done = false;
       while (!inner_done && its < maxiter) {
-        std::vector<double> cycle_start = rnorm;
+        std::vector<double> cycle_start(hG.rn2, hG.rn2 + R);
         int j = 0;
+        bool any = true;
         for (; j < restart && its < maxiter; ++j) {
           // z = M r (FP32 network) or z = r, then w = D(m) z at the inner precision
           if (net) {
             blas_convert(OVL_F64, rin.p, OVL_F32, r32.p, N, R, s);
-            for (int r = 0; r < R; ++r)
-              if (active[r]) net_apply(net, u, vec(r32.p, v32, r), vec(z32.p, v32, r), s);
+            net_apply(net, u, r32.p, z32.p, R, s);
             blas_convert(OVL_F32, z32.p, P, zP.p, N, R, s);
           } else {
             blas_convert(OVL_F64, rin.p, P, zP.p, N, R, s);
@@ -588,70 +676,54 @@ int fgcr_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, do
           blas_convert(P, wP.p, OVL_F64, w64.p, N, R, s);
           blas_convert(P, zP.p, OVL_F64, z64.p, N, R, s);
           ++its;
-          bool any = false;
+          // w, z -= (own earlier directions) (W^dag w), twice
+          const int nb = j * R;
+          for (int pass = 0; pass < (j > 0 ? 2 : 0); ++pass) {
+            block_dot(g, Wb.p, nb, w64.p, OVL_F64, R, static_cast<double2*>(Cb.p), s);
+            hipLaunchKernelGGL(gcr_coef_kernel, dim3((nb * R + 255) / 256), dim3(256), 0, s, nb * R, R,
+                               static_cast<const double2*>(Cb.p), static_cast<double2*>(Kb.p), dG);
+            block_axpy(g, Wb.p, nb, static_cast<const double2*>(Kb.p), w64.p, OVL_F64, R, true, s);
+            block_axpy(g, Zb.p, nb, static_cast<const double2*>(Kb.p), z64.p, OVL_F64, R, true, s);
+          }
+          // W_j = w / ||w||, Z_j = z / ||w||
+          blas_norm2(OVL_F64, n16, w64.p, R, v64, dG->tmp, s);
+          hipLaunchKernelGGL(gcr_norm_kernel, dim3(1), dim3(64), 0, s, R, dG);
+          hipLaunchKernelGGL(gcr_store_kernel, sgrid, dim3(256), 0, s, n16, v64,
+                             static_cast<const double2*>(w64.p), reinterpret_cast<double2*>(blk(Wb.p, j)), dG);
+          hipLaunchKernelGGL(gcr_store_kernel, sgrid, dim3(256), 0, s, n16, v64,
+                             static_cast<const double2*>(z64.p), reinterpret_cast<double2*>(blk(Zb.p, j)), dG);
+          // alpha = W_j^dag r; e += alpha Z_j; r -= alpha W_j
+          blas_dot(OVL_F64, n16, blk(Wb.p, j), rin.p, R, v64, dG->dot, s);
+          hipLaunchKernelGGL(gcr_alpha_kernel, dim3(1), dim3(64), 0, s, R, dG);
+          blas_axpby(OVL_F64, blk(Zb.p, j), dG->alpha, OVL_F64, e64.p, dG->one, N, R, s);
+          blas_axpby(OVL_F64, blk(Wb.p, j), dG->malpha, OVL_F64, rin.p, dG->one, N, R, s);
+          blas_norm2(OVL_F64, n16, rin.p, R, v64, dG->tmp, s);
+          hipLaunchKernelGGL(gcr_check_kernel, dim3(1), dim3(64), 0, s, R, dG);
+          OVL_HIP(hipGetLastError());
+          OVL_HIP(hipMemcpyAsync(&hG, dG, sizeof(GcrScalars), hipMemcpyDeviceToHost, s));
+          OVL_HIP(hipStreamSynchronize(s));
+          any = false;
           for (int r = 0; r < R; ++r) {
-            if (!active[r]) continue;
-            char* wr = vec(w64.p, v64, r);
-            char* zr = vec(z64.p, v64, r);
-            char* Wr = vec(Wb.p, v64, r * restart);
-            char* Zr = vec(Zb.p, v64, r * restart);
-            for (int pass = 0; pass < (j > 0 ? 2 : 0); ++pass) {
-              block_dot(g, Wr, j, wr, OVL_F64, 1, static_cast<double2*>(cb.p), s);
-              std::vector<double2> hc(j);
-              OVL_HIP(hipMemcpyAsync(hc.data(), cb.p, sizeof(double2) * j, hipMemcpyDeviceToHost, s));
-              OVL_HIP(hipStreamSynchronize(s));
-              for (auto& v : hc) v = make_double2(-v.x, -v.y);
-              OVL_HIP(hipMemcpyAsync(cb.p, hc.data(), sizeof(double2) * j, hipMemcpyHostToDevice, s));
-              block_axpy(g, Wr, j, static_cast<const double2*>(cb.p), wr, OVL_F64, 1, true, s);
-              block_axpy(g, Zr, j, static_cast<const double2*>(cb.p), zr, OVL_F64, 1, true, s);
-              OVL_HIP(hipStreamSynchronize(s));
-            }
-            std::vector<double> nw;
-            norms(wr, 1, v64, OVL_F64, nw);
-            const double nrm = std::sqrt(nw[0]);
-            if (!(nrm > 0.0) || !std::isfinite(nrm)) {
-              fallback = true;
-              break;
-            }
-            std::vector<double> sv = {1.0 / nrm, 0.0};
-            dev_scalars(sv);
-            blas_axpby(OVL_F64, wr, dsc, OVL_F64, vec(Wr, v64, j), nullptr, N, 1, s);
-            blas_axpby(OVL_F64, zr, dsc, OVL_F64, vec(Zr, v64, j), nullptr, N, 1, s);
-            const std::complex<double> alpha = dot1(vec(Wr, v64, j), vec(rin.p, v64, r));
-            axpy1(vec(Zr, v64, j), vec(e64.p, v64, r), alpha);
-            axpy1(vec(Wr, v64, j), vec(rin.p, v64, r), -alpha);
-            std::vector<double> rr;
-            norms(vec(rin.p, v64, r), 1, v64, OVL_F64, rr);
-            rnorm[r] = std::sqrt(rr[0]);
-            if (!std::isfinite(rnorm[r])) {
-              fallback = true;
-              break;
-            }
-            if (rnorm[r] <= target[r]) active[r] = 0;
-            any = any || active[r];
+            if (hG.bad[r]) fallback = true;
+            any = any || hG.active[r];
           }
           if (fallback || !any) break;
         }
         if (fallback) break;
-        bool any = false, stagnant = false;
+        bool stagnant = false;
         for (int r = 0; r < R; ++r)
-          if (active[r]) {
-            any = true;
-            if (j >= restart && rnorm[r] > 0.9 * cycle_start[r]) stagnant = true;
-          }
+          if (hG.active[r] && j >= restart && hG.rn2[r] > 0.81 * cycle_start[r]) stagnant = true;
         if (stagnant) fallback = true;
         inner_done = !any || fallback;
       }
       // x += scale * e
-      std::vector<double> scv(2 * OVL_MAX_RHS, 0.0);
-      for (int r = 0; r < R; ++r) scv[2 * r] = scale[r];
+      std::vector<double> scv(4 * OVL_MAX_RHS, 0.0);
+      for (int r = 0; r < R; ++r) {
+        scv[2 * r] = scale[r];
+        scv[2 * OVL_MAX_RHS + 2 * r] = 1.0;
+      }
       dev_scalars(scv);
-      std::vector<double> onev(2 * OVL_MAX_RHS, 0.0);
-      WsBuf oneb(sizeof(double) * 2 * OVL_MAX_RHS, s);
-      for (int r = 0; r < R; ++r) onev[2 * r] = 1.0;
-      OVL_HIP(hipMemcpyAsync(oneb.p, onev.data(), sizeof(double) * onev.size(), hipMemcpyHostToDevice, s));
-      OVL_HIP(hipStreamSynchronize(s));
-      blas_axpby(OVL_F64, e64.p, dsc, OVL_F64, x, static_cast<double*>(oneb.p), N, R, s);
+      blas_axpby(OVL_F64, e64.p, dsc, OVL_F64, x, dsc + 2 * OVL_MAX_RHS, N, R, s);
       OVL_HIP(hipStreamSynchronize(s));
       if (fallback) break;
     }

@@ -83,6 +83,7 @@ class SolveOpts(ctypes.Structure):
         ("inner_sign", ctypes.c_void_p),
         ("chiral", ctypes.c_int),
         ("deflation", ctypes.c_void_p),
+        ("harvest_stride", ctypes.c_int),
     ]
 
 

@@ -92,6 +92,62 @@ def test_harvested_pairs_are_exact(setup):
         assert gu.rel_err(B[i], sign.overlap_apply(lat, U, X[i], 1.5, 0.05, so)) < 1e-6
 
 
+def test_harvest_stride_takes_every_kth_iteration(setup):
+    """With harvest_stride k the pairs are those of inner iterations 0, k,
+    2k, ...: bit-identical to the matching pairs of an every-iteration
+    harvest of the same (deterministic) solve, and still exact pairs."""
+    lat, U, g, gauge = setup
+    s = ovl.Sign(0.4, 6.6, n=60)
+    b = si.point_sources(DIMS)[:2]
+    out = {}
+    for stride, cap in ((1, 12), (5, 4)):
+        x = gu.pack(g, np.zeros_like(b), ovl.OVL_F64, 2)
+        hx, hb = gu.empty_field(g, F32, cap), gu.empty_field(g, F32, cap)
+        opts = ovl.SolveOpts(ovl.OVL_F64, 0.0, 0, 1, 50, hx.data_ptr(), hb.data_ptr(), cap)
+        opts.harvest_stride = stride
+        st = ovl.SolveStats()
+        ovl.ovl_cg_solve(x, gu.pack(g, b, ovl.OVL_F64, 2), 2, gauge, 1.5, 0.05, s, None, 1e-10, 5000, opts,
+                         ctypes.byref(st), None)
+        assert st.harvested == cap
+        out[stride] = (gu.unpack(g, hx, F32, cap), gu.unpack(g, hb, F32, cap))
+    # two rhs per iteration: pair 2 i + r of stride 5 is iteration 5 i, pair 2 (5 i) + r of stride 1
+    for k5, k1 in ((0, 0), (1, 1), (2, 10), (3, 11)):
+        assert np.array_equal(out[5][0][k5], out[1][0][k1]) and np.array_equal(out[5][1][k5], out[1][1][k1])
+    from oracle import sign
+    so = sign.SignApprox(lam_max=6.6, eps=s.eps, coeffs=s.coeffs())
+    assert gu.rel_err(out[5][1][3], sign.overlap_apply(lat, U, out[5][0][3], 1.5, 0.05, so)) < 1e-6
+
+
+def test_fgcr_batch_matches_single_rhs(setup):
+    """The lockstep batched FGCR (3 rhs, with a network and with M = 1)
+    gives each rhs the solution of its own single-rhs FGCR solve, both at the
+    FP64 true residual 1e-10."""
+    lat, U, g, gauge = setup
+    s = ovl.Sign(0.4, 6.6, n=60)
+    net = ovl.Net(g, 4)
+    w1, w2 = _w(41, 4, 1, 0.005), _w(42, 1, 4, 0.005)  # M: 1/rho plus a small learned-like part
+    w1[0, 0, 0] += np.eye(4)
+    w2[0, 0, 0] += np.eye(4) / 1.5
+    net.set_weights(w1, w2)
+    b = si.point_sources(DIMS)[[3, 9, 5]]
+    for M in (net, None):
+        opts = ovl.SolveOpts(F32, 1e-5, 0, 1, 50, None, None, 0)
+        x = gu.pack(g, np.zeros_like(b), ovl.OVL_F64, 3)
+        st = ovl.SolveStats()
+        rc = ovl.ovl_fgcr_solve(x, gu.pack(g, b, ovl.OVL_F64, 3), 3, gauge, 1.5, 0.05, s, None, M, 8, 1e-10, 3000,
+                                opts, ctypes.byref(st), None)
+        print("batched FGCR (%s): %d iterations, fallback %d" % ("net" if M else "M=1", st.iterations,
+                                                                 st.fallback_used))
+        assert rc == 0 and st.fallback_used == 0 and max(st.true_residual[:3]) <= 1e-10
+        xb = gu.unpack(g, x, ovl.OVL_F64, 3)
+        for r in range(3):
+            x1 = gu.pack(g, np.zeros_like(b[r]), ovl.OVL_F64, 1)
+            s1 = ovl.SolveStats()
+            assert ovl.ovl_fgcr_solve(x1, gu.pack(g, b[r], ovl.OVL_F64, 1), 1, gauge, 1.5, 0.05, s, None, M, 8, 1e-10,
+                                      3000, opts, ctypes.byref(s1), None) == 0
+            assert gu.rel_err(xb[r], gu.unpack(g, x1, ovl.OVL_F64, 1)) < 1e-7
+
+
 def test_training_reduces_loss_and_fgcr(setup):
     lat, U, g, gauge = setup
     npairs = 48
