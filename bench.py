@@ -439,11 +439,31 @@ def c2_block(ovl, args):
         st = ovl.SolveStats()
         rc = ovl.ovl_cg_solve(xs, b64, 1, gauge, rho, m, sgn, lm, 1e-10, 20000, opts, st, None)
         rec["cg"] = {"rc": rc, "seconds": round(st.seconds, 3), "iterations": st.iterations, "restarts": st.restarts,
-                     "true_residual": st.true_residual[0], "sign_applies": st.sign_applies}
+                     "true_residual": st.true_residual[0], "sign_applies": st.sign_applies,
+                     "dslash_applies": st.dslash_applies}
         log("C2 %s: %s" % (name, rec))
         out[name] = rec
     out["cg_speedup_f16_vs_f64"] = round(out["f64"]["cg"]["seconds"] / out["f16"]["cg"]["seconds"], 2)
     out["cg_speedup_f32_vs_f64"] = round(out["f64"]["cg"]["seconds"] / out["f32"]["cg"]["seconds"], 2)
+    # adaptive precision (Sec. V): the same F16-inner solve with coarser
+    # inner signs allowed in the cycles that need less than inner_tol
+    relax = [ovl.Sign(abs(lams[-1]), lam_max, delta=d) for d in (1e-2, 1e-1)]
+    arr = (ctypes.c_void_p * 2)(*[r.handle.value for r in relax])
+    opts = ovl.SolveOpts(ovl.OVL_F16, 1e-3, 8, 1, 60, None, None, 0, sgn_in.handle.value)
+    opts.relax_signs = ctypes.cast(arr, ctypes.c_void_p).value
+    opts.n_relax = 2
+    xs = torch.zeros(g.spinor_bytes(ovl.OVL_F64), dtype=torch.uint8, device=dev)
+    st = ovl.SolveStats()
+    rc = ovl.ovl_cg_solve(xs, b64, 1, gauge, rho, m, sgn, lm, 1e-10, 20000, opts, st, None)
+    base = out["f16"]["cg"]
+    out["adaptive_sign_f16"] = {"rc": rc, "seconds": round(st.seconds, 3), "iterations": st.iterations,
+                                "restarts": st.restarts, "sign_applies": st.sign_applies,
+                                "dslash_applies": st.dslash_applies, "true_residual": st.true_residual[0],
+                                "fixed_inner_sign": {"n": sgn_in.n, "seconds": base["seconds"],
+                                                     "sign_applies": base["sign_applies"],
+                                                     "dslash_applies": base["dslash_applies"]},
+                                "relax_signs_n": [r.n for r in relax]}
+    log("C2 adaptive inner sign: %s" % out["adaptive_sign_f16"])
     if args.defl_ell > 0:
         out["deflation"] = deflation_block(ovl, g, gauge, rho, m, sgn, sgn_in, lm, b64, args.defl_ell, out)
     del lm, V

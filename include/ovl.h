@@ -269,6 +269,16 @@ int ovl_overlap_apply(void* out, const void* in, const ovl_gauge* u, double rho,
  *   CG solves only for r minus its components along the xi_i, at the reduced
  *   condition number ||D|| / |d_l'|; the cycles repeat until the FP64 true
  *   residual meets tol, so approximate eigenpairs only cost extra cycles.
+ *   opts->relax_signs (adaptive precision, Sec. V): the accuracy of the
+ *   inner operator's sign is chosen per defect-correction cycle.  The first
+ *   cycle uses inner_sign; each cycle's residual reduction f, run with sign
+ *   error delta, gives the error constant K = f / delta of a correction
+ *   (from above when inner_tol limited the cycle).  A later cycle takes the
+ *   coarsest of inner_sign and relax_signs with K delta within the reduction
+ *   that remains to reach tol, so cycles that must gain the full inner_tol
+ *   keep inner_sign and the last ones, which need less, run cheaper.  A
+ *   cycle that gains less than a factor 2 sends the next one back to
+ *   inner_sign.  The FP64 true residual always uses `sign`.
  *   opts may be NULL (plain FP64, no graph).  Work is done on a private
  *   stream ordered after, and before, the caller's stream s.
  * ovl_propagator: out = (1 - D/2) x (Sec. II), the propagator from a
@@ -294,6 +304,10 @@ typedef struct {
   int harvest_stride;  /* harvest the pairs of every stride-th inner
                           iteration (<= 1: every one), so a capped harvest
                           spans the whole solve                           */
+  const ovl_sign* const* relax_signs; /* CG only (adaptive precision, Sec.
+                          V): n_relax coarser inner signs, delta increasing,
+                          same lam_max; NULL = off.  Not with chiral.     */
+  int n_relax;
 } ovl_solve_opts;
 
 typedef struct {

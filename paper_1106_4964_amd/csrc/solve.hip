@@ -181,6 +181,25 @@ int cg_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, doub
   S.per_sign_dw_in = 2 * (static_cast<int64_t>(S.sg_in->c.size()) - 1) + 1;
   int recon = 0;
   (void)gauge_links(u, P, &recon);  // the inner precision must have links
+  // adaptive precision: the inner sign and the coarser ones the solve may
+  // switch to as the inner residual drops
+  std::vector<const ovl_sign*> ladder{S.sg_in};
+  if (opt.relax_signs && opt.n_relax > 0) {
+    OVL_REQUIRE(!chiral, OVL_E_ARG, "relaxed inner signs do not combine with chiral solves");
+    OVL_REQUIRE(opt.n_relax <= 8, OVL_E_ARG, "at most 8 relax signs");
+    for (int k = 0; k < opt.n_relax; ++k) {
+      const ovl_sign* rs = opt.relax_signs[k];
+      OVL_REQUIRE(rs && rs->lam_max == sg->lam_max, OVL_E_ARG, "relax signs must share lam_max with sign");
+      OVL_REQUIRE(rs->delta > ladder.back()->delta, OVL_E_ARG, "relax signs must have increasing delta");
+      ladder.push_back(rs);
+    }
+  }
+  int level = 0;
+  auto set_level = [&](int lv) {
+    level = lv;
+    S.sg_in = ladder[lv];
+    S.per_sign_dw_in = 2 * (static_cast<int64_t>(S.sg_in->c.size()) - 1) + 1;
+  };
 
   // private stream (graph capture needs one), ordered after the caller's work
   hipStream_t s;
@@ -194,9 +213,20 @@ int cg_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, doub
   // workspace kept for that stream can serve this solve
   ws_retire_stream(us, s);
 
-  hipGraphExec_t gexec = nullptr;
-  hipGraph_t graph = nullptr;
-  bool graph_chiral = false;
+  // one captured chunk per inner sign (the sign's coefficients are kernel
+  // arguments); a chunk captured for the chiral operator is recaptured when
+  // the solve leaves chiral mode
+  std::vector<hipGraphExec_t> gexecs(ladder.size(), nullptr);
+  std::vector<hipGraph_t> graphs(ladder.size(), nullptr);
+  std::vector<char> graph_chiral(ladder.size(), 0);
+  auto drop_graphs = [&]() {
+    for (size_t k = 0; k < ladder.size(); ++k) {
+      if (gexecs[k]) (void)hipGraphExecDestroy(gexecs[k]);
+      if (graphs[k]) (void)hipGraphDestroy(graphs[k]);
+      gexecs[k] = nullptr;
+      graphs[k] = nullptr;
+    }
+  };
   int rc = OVL_OK;
   try {
     WsBuf r64(S.v64 * R, s), tmp64(S.v64 * R, s), e64(S.v64 * R, s);
@@ -268,6 +298,10 @@ int cg_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, doub
     int its = 0;
     bool chiral_failed = false;
     double prev_worst_chiral = 0.0;
+    // adaptive precision: error constant of a correction per unit sign error
+    // (conservative start: the first cycle runs with the finest inner sign)
+    const double k_sign_min = 1.0;
+    double k_sign = INFINITY, prev_worst = 0.0, cycle_delta = ladder[0]->delta;
     st->restarts = 0;
     for (;;) {
       // true residual r = b - D(m) x in FP64
@@ -288,6 +322,14 @@ int cg_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, doub
       }
       if (log_on())
         fprintf(stderr, "[ovl cg] cycle %d: %d iterations, max FP64 true residual %.3e\n", st->restarts, its, worst);
+      if (ladder.size() > 1 && prev_worst > 0.0) {
+        // adaptive precision: a cycle run with sign error delta reduced the
+        // residual by f; f / delta bounds the error constant of the
+        // correction (from above when the cycle was limited by inner_tol)
+        const double f = worst / prev_worst;
+        k_sign = f < 0.5 ? std::max(k_sign_min, f / cycle_delta) : INFINITY;
+      }
+      prev_worst = worst;
       if (done) break;
       if (opt.deflation) {
         // eq. 9: the low part of the correction at once; the inner solve is
@@ -320,6 +362,24 @@ int cg_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, doub
 
       // inner system D e = r / scale, scale chosen so the rms element of the
       // scaled residual is O(1/8) (keeps FP16 iterates away from under/overflow)
+      // adaptive precision: this cycle's inner sign is the coarsest whose
+      // error, times the constant measured on the earlier cycles, stays
+      // within the reduction that remains to reach tol (cycles that must
+      // gain the full inner_tol keep the finest inner sign)
+      if (ladder.size() > 1) {
+        double need = 1.0;
+        for (int r = 0; r < R; ++r) {
+          const double rn = std::sqrt(rn2[r]);
+          if (st->true_residual[r] > tol && rn > 0.0) need = std::min(need, 0.5 * tol * std::sqrt(bn2[r]) / rn);
+        }
+        int lv = 0;
+        while (lv + 1 < static_cast<int>(ladder.size()) && k_sign * ladder[lv + 1]->delta <= need) ++lv;
+        if (log_on() && lv != level)
+          fprintf(stderr, "[ovl cg] cycle %d: inner sign n = %d (delta %.1e)\n", st->restarts,
+                  static_cast<int>(ladder[lv]->c.size()) - 1, ladder[lv]->delta);
+        set_level(lv);
+        cycle_delta = ladder[lv]->delta;
+      }
       for (int r = 0; r < R; ++r) {
         const double rn = std::sqrt(rn2[r]);
         const bool act = st->true_residual[r] > tol && rn > 0.0;
@@ -354,7 +414,9 @@ int cg_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, doub
       for (;;) {
         int step;
         if (opt.graph_chunk > 0 && inner > 0 && !harvest) {
-          if (gexec && graph_chiral != chiral) {
+          hipGraphExec_t& gexec = gexecs[level];
+          hipGraph_t& graph = graphs[level];
+          if (gexec && (graph_chiral[level] != 0) != chiral) {
             OVL_HIP(hipGraphExecDestroy(gexec));
             OVL_HIP(hipGraphDestroy(graph));
             gexec = nullptr;
@@ -365,7 +427,7 @@ int cg_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, doub
             OVL_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
             const int64_t sa = st->sign_applies, da = st->dslash_applies;
             for (int k = 0; k < opt.graph_chunk; ++k) chiral ? body_chiral() : body();
-            graph_chiral = chiral;
+            graph_chiral[level] = chiral ? 1 : 0;
             st->sign_applies = sa;  // captured, not executed: counted at replay
             st->dslash_applies = da;
             OVL_HIP(hipStreamEndCapture(s, &graph));
@@ -421,16 +483,17 @@ int cg_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, doub
     st->iterations = its;
     OVL_HIP(hipStreamSynchronize(s));
   } catch (...) {
-    if (gexec) (void)hipGraphExecDestroy(gexec);
-    if (graph) (void)hipGraphDestroy(graph);
+    drop_graphs();
     (void)hipStreamSynchronize(s);
     (void)hipEventDestroy(ev);
     ws_retire_stream(s, us);
     (void)hipStreamDestroy(s);
     throw;
   }
-  if (gexec) OVL_HIP(hipGraphExecDestroy(gexec));
-  if (graph) OVL_HIP(hipGraphDestroy(graph));
+  for (size_t k = 0; k < ladder.size(); ++k) {
+    if (gexecs[k]) OVL_HIP(hipGraphExecDestroy(gexecs[k]));
+    if (graphs[k]) OVL_HIP(hipGraphDestroy(graphs[k]));
+  }
   // the caller's stream continues after the solve
   OVL_HIP(hipEventRecord(ev, s));
   OVL_HIP(hipStreamWaitEvent(us, ev, 0));

@@ -84,6 +84,8 @@ class SolveOpts(ctypes.Structure):
         ("chiral", ctypes.c_int),
         ("deflation", ctypes.c_void_p),
         ("harvest_stride", ctypes.c_int),
+        ("relax_signs", ctypes.c_void_p),
+        ("n_relax", ctypes.c_int),
     ]
 
 

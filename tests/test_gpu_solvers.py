@@ -183,6 +183,45 @@ def test_cg_relaxed_inner_sign(c1, c1_lowmodes, prec):
         assert np.linalg.norm(res) / np.linalg.norm(b[r]) <= 1.05e-10
 
 
+@pytest.mark.parametrize("graph", [0, 4])
+def test_cg_adaptive_precision_sign(c1, c1_lowmodes, graph):
+    """Adaptive precision (Sec. V): the F16 inner solves use the delta = 1e-3
+    sign and may move to coarser ones (1e-2, 1e-1) in the last cycles, whose
+    remaining reduction is small.  The FP64 true residual still reaches
+    1e-10, judged by the oracle's operator, with no more D_w applications
+    than the fixed inner sign (2% slack); a ladder out of delta order is
+    refused."""
+    V, lam = c1_lowmodes
+    g = ovl.Geometry(c1["dims"])
+    gauge = gu.make_gauge(g, c1["U"], [(ovl.OVL_F16, 1)])
+    lm = ovl.LowModes(g, gu.pack(g, V, ovl.OVL_F64, len(V)), lam)
+    s = ovl.Sign(abs(lam[-1]), c1["hi"], delta=1e-12)
+    ladder = [ovl.Sign(abs(lam[-1]), c1["hi"], delta=d) for d in (1e-3, 1e-2, 1e-1)]
+    assert ladder[0].n > ladder[1].n > ladder[2].n
+    so = sign.SignApprox(lam_max=c1["hi"], eps=s.eps, coeffs=s.coeffs())
+    b = si.point_sources(c1["dims"])
+    runs = {}
+    for name, rel in (("fixed", []), ("adaptive", ladder[1:])):
+        arr = (ctypes.c_void_p * 2)(*[r.handle.value for r in rel]) if rel else None
+        opts = ovl.SolveOpts(ovl.OVL_F16, 1e-3, graph, 1, 60, None, None, 0, ladder[0].handle.value)
+        opts.relax_signs = ctypes.cast(arr, ctypes.c_void_p).value if arr is not None else None
+        opts.n_relax = len(rel)
+        rc, x, st = _solve_opts(g, gauge, s, lm, b, 0.01, opts)
+        assert rc == 0, list(st.true_residual)
+        runs[name] = (st.iterations, st.restarts, st.dslash_applies)
+        for r in (0, 6, 11):
+            res = b[r] - sign.overlap_apply(c1["lat"], c1["U"], x[r], RHO, 0.01, so, V, lam)
+            assert np.linalg.norm(res) / np.linalg.norm(b[r]) <= 1.05e-10
+    print("inner sign n = %d/%d/%d, (iterations, cycles, D_w applies):" % tuple(l.n for l in ladder), runs)
+    assert runs["adaptive"][2] <= 1.02 * runs["fixed"][2]
+    bad = (ctypes.c_void_p * 2)(ladder[2].handle.value, ladder[1].handle.value)
+    opts = ovl.SolveOpts(ovl.OVL_F16, 1e-3, graph, 1, 60, None, None, 0, ladder[0].handle.value)
+    opts.relax_signs = ctypes.cast(bad, ctypes.c_void_p).value
+    opts.n_relax = 2
+    with pytest.raises(ovl.OvlError):
+        _solve_opts(g, gauge, s, lm, b[:1], 0.01, opts)
+
+
 def _solve_opts(g, gauge, s, lm, b, m, opts, maxiter=5000):
     R = b.shape[0]
     x = gu.pack(g, np.zeros_like(b), ovl.OVL_F64, R)
