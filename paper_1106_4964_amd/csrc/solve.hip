@@ -837,6 +837,124 @@ int fgcr_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, do
 // tolerance.  Then x_j = D(m_j)^dag y_j / c_j, and each x_j goes through
 // the FP64 defect-correction loop of cg_solve (which also absorbs the O(delta)
 // difference between D D^dag and c (K + sigma) of the polynomial sign).
+namespace {
+
+constexpr int MM_MAX = 8;  // masses
+
+// Device scalars of the shifted CG stage, one slot per (mass, rhs).
+struct MMScalars {
+  double zeta[MM_MAX][OVL_MAX_RHS], zeta_p[MM_MAX][OVL_MAX_RHS], zn[MM_MAX][OVL_MAX_RHS];
+  double alpha_j[MM_MAX][OVL_MAX_RHS];
+  double coef[MM_MAX][OVL_MAX_RHS][4];  // alpha_j, zeta_next, beta_j, active (for the fused update)
+  double sig[MM_MAX];                   // sigma_j - sigma_base
+  double alpha_p[OVL_MAX_RHS], beta_p[OVL_MAX_RHS], rr[OVL_MAX_RHS], bn2[OVL_MAX_RHS];
+  double alpha[OVL_MAX_RHS];
+  double dot[2 * OVL_MAX_RHS];   // reduction outputs, (re, im) per rhs
+  double nrm[2 * OVL_MAX_RHS];
+  double malpha[2 * OVL_MAX_RHS];  // (-alpha, 0) per rhs
+  double one[2 * OVL_MAX_RHS];
+  double rel;
+  int act[MM_MAX][OVL_MAX_RHS];
+  int live[OVL_MAX_RHS];
+  int bad[OVL_MAX_RHS];  // 1 breakdown (p^dag A p <= 0), 2 NaN/Inf
+};
+
+// alpha = rr / p^dag A p per live rhs, and every shift's step alpha_j from
+// the zeta recurrence (Jegerlehner); one thread per rhs.
+__global__ void mm_alpha_kernel(int R, int nm, int base, MMScalars* S) {
+  const int r = threadIdx.x;
+  if (r >= R) return;
+  double a = 0.0;
+  if (S->live[r]) {
+    const double pq = S->dot[2 * r];
+    if (!(pq == pq) || isinf(pq)) {
+      S->bad[r] = 2;
+      S->live[r] = 0;
+    } else if (pq <= 0.0) {
+      S->bad[r] = 1;
+      S->live[r] = 0;
+    } else {
+      a = S->rr[r] / pq;
+    }
+  }
+  S->alpha[r] = a;
+  S->malpha[2 * r] = -a;
+  S->malpha[2 * r + 1] = 0.0;
+  for (int j = 0; j < nm; ++j) {
+    double z = 1.0, aj = a;
+    if (j != base && S->live[r]) {
+      const double zc = S->zeta[j][r], zp = S->zeta_p[j][r];
+      const double den = a * S->beta_p[r] * (zp - zc) + zp * S->alpha_p[r] * (1.0 + S->sig[j] * a);
+      z = den != 0.0 ? zc * zp * S->alpha_p[r] / den : 0.0;
+      aj = zc != 0.0 ? a * z / zc : 0.0;
+    }
+    S->zn[j][r] = S->live[r] ? z : S->zeta[j][r];
+    S->alpha_j[j][r] = (S->live[r] && S->act[j][r]) ? aj : 0.0;
+  }
+}
+
+// beta from the new residual, the fused-update coefficients, then the
+// shifted state for the next iteration and the convergence of each shift
+// (its residual is zeta_j r).
+__global__ void mm_beta_kernel(int R, int nm, MMScalars* S) {
+  const int r = threadIdx.x;
+  if (r >= R) return;
+  const double rrn = S->nrm[2 * r];
+  const bool live = S->live[r] != 0;
+  if (live && (!(rrn == rrn) || isinf(rrn))) {
+    S->bad[r] = 2;
+    S->live[r] = 0;
+  }
+  const bool ok = S->live[r] != 0;
+  const double beta = ok ? rrn / S->rr[r] : 0.0;
+  int any = 0;
+  for (int j = 0; j < nm; ++j) {
+    const bool on = ok && S->act[j][r];
+    const double zc = S->zeta[j][r], zn = S->zn[j][r];
+    const double ratio = (zc != 0.0) ? zn / zc : 0.0;
+    S->coef[j][r][0] = S->alpha_j[j][r];
+    S->coef[j][r][1] = on ? zn : 0.0;
+    S->coef[j][r][2] = on ? beta * ratio * ratio : 1.0;
+    S->coef[j][r][3] = on ? 1.0 : 0.0;
+    if (ok) {
+      S->zeta_p[j][r] = zc;
+      S->zeta[j][r] = zn;
+      if (S->act[j][r] && fabs(zn) * sqrt(rrn) <= S->rel * sqrt(S->bn2[r])) S->act[j][r] = 0;
+    }
+    any |= S->act[j][r];
+  }
+  if (ok) {
+    S->alpha_p[r] = S->alpha[r];
+    S->beta_p[r] = beta;
+    S->rr[r] = rrn;
+    S->live[r] = any;
+  }
+}
+
+// For every FP64 element of rhs r (blockIdx.y) and every shift j with its
+// coefficient row active: y_j += alpha_j p_j, then p_j = zeta_j r + beta_j p_j
+// (the base residual is read once for all shifts).
+__global__ void mm_update_kernel(size_t n16, int R, int nm, const double2* __restrict__ res, double2* Y, double2* Pj,
+                                 const MMScalars* S) {
+  const int r = blockIdx.y;
+  const size_t e = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x;
+  if (e >= n16) return;
+  const double2 rv = res[r * n16 + e];
+  for (int j = 0; j < nm; ++j) {
+    const double* c = S->coef[j][r];
+    if (c[3] == 0.0 && c[0] == 0.0) continue;
+    const size_t o = (static_cast<size_t>(j) * R + r) * n16 + e;
+    const double2 pv = Pj[o];
+    double2 yv = Y[o];
+    yv.x = fma(c[0], pv.x, yv.x);
+    yv.y = fma(c[0], pv.y, yv.y);
+    Y[o] = yv;
+    if (c[3] != 0.0) Pj[o] = make_double2(fma(c[1], rv.x, c[2] * pv.x), fma(c[1], rv.y, c[2] * pv.y));
+  }
+}
+
+}  // namespace
+
 int cg_multimass(void* const* xs, const void* b, int R, const ovl_gauge* u, double rho, const double* masses, int nm,
                  const ovl_sign* sg, const ovl_lowmodes* lm, double tol, int maxiter, const ovl_solve_opts* o,
                  ovl_solve_stats* sts, hipStream_t us) {
@@ -917,21 +1035,40 @@ int cg_multimass(void* const* xs, const void* b, int R, const ovl_gauge* u, doub
       blas_axpby(OVL_F64, b, A0, OVL_F64, vec(pj.p, j), nullptr, N, R, s);
       blas_zero(vec(yj.p, j), v64 * R, s);
     }
-    std::vector<double> bn2 = reduce(b, nullptr), rr = bn2;
+    const std::vector<double> bn2 = reduce(b, nullptr);
     for (int r = 0; r < R; ++r) OVL_REQUIRE(std::isfinite(bn2[r]), OVL_E_NAN, "right-hand side contains NaN or Inf");
-    const double rel = std::max(0.5 * tol, P == OVL_F64 ? 0.0 : inner_tol);
-    std::vector<std::vector<double>> zeta(nm, std::vector<double>(R, 1.0)), zeta_p = zeta;
-    std::vector<std::vector<int>> act(nm, std::vector<int>(R, 1));
-    for (int j = 0; j < nm; ++j)
-      for (int r = 0; r < R; ++r) act[j][r] = bn2[r] > 0.0;
-    std::vector<double> alpha_p(R, 1.0), beta_p(R, 0.0);
+    // the shifted state lives on the device; the host reads the flags once
+    // per iteration
+    WsBuf mmb(sizeof(MMScalars), s);
+    MMScalars* dM = static_cast<MMScalars*>(mmb.p);
+    MMScalars hM{};
+    hM.rel = std::max(0.5 * tol, P == OVL_F64 ? 0.0 : inner_tol);
+    for (int j = 0; j < nm; ++j) hM.sig[j] = sigma[j] - sigma[base];
+    for (int r = 0; r < R; ++r) {
+      hM.rr[r] = bn2[r];
+      hM.bn2[r] = bn2[r];
+      hM.alpha_p[r] = 1.0;
+      hM.beta_p[r] = 0.0;
+      hM.one[2 * r] = 1.0;
+      hM.live[r] = bn2[r] > 0.0;
+      for (int j = 0; j < nm; ++j) {
+        hM.zeta[j][r] = hM.zeta_p[j][r] = 1.0;
+        hM.act[j][r] = bn2[r] > 0.0;
+      }
+    }
+    OVL_HIP(hipMemcpyAsync(dM, &hM, sizeof(MMScalars), hipMemcpyHostToDevice, s));
+    upload(ones, ones, zeros, zeros);  // A0 = A1 = 1 for the q assembly, for the whole stage
+    const size_t n16 = v64 / 16;
+    int live_flags[2 * OVL_MAX_RHS];
     while (its < maxiter) {
-      std::vector<int> live(R, 0);
+      OVL_HIP(hipMemcpyAsync(live_flags, dM->live, sizeof(int) * 2 * OVL_MAX_RHS, hipMemcpyDeviceToHost, s));
+      OVL_HIP(hipStreamSynchronize(s));  // live and bad are adjacent
       bool any = false;
-      for (int r = 0; r < R; ++r)
-        for (int j = 0; j < nm; ++j)
-          if (act[j][r]) live[r] = 1;
-      for (int r = 0; r < R; ++r) any = any || live[r];
+      for (int r = 0; r < R; ++r) {
+        if (live_flags[OVL_MAX_RHS + r] == 2) throw Error(OVL_E_NAN, "NaN or Inf in a multi-mass CG iterate");
+        if (live_flags[OVL_MAX_RHS + r] == 1) throw Error(OVL_E_BREAKDOWN, "multi-mass CG breakdown: p^dag A p <= 0");
+        any = any || live_flags[r];
+      }
       if (!any) break;
       // q = (K + sigma_0) p_0 at the inner precision
       void* p0 = vec(pj.p, base);
@@ -940,78 +1077,21 @@ int cg_multimass(void* const* xs, const void* b, int R, const ovl_gauge* u, doub
       overlap_combine_dag(tP.p, pP.p, u, rho, 0.0, 1.0, sg_in, lm, P, R, s);
       blas_convert(P, qP.p, OVL_F64, q64.p, N, R, s);
       blas_convert(P, tP.p, OVL_F64, t64.p, N, R, s);
-      upload(ones, ones, zeros, zeros);
       blas_axpby(OVL_F64, t64.p, A0, OVL_F64, q64.p, A1, N, R, s);
       s0.sign_applies += 2 * R;
       s0.dslash_applies += 2 * R * per_sign_dw_in;
-      const std::vector<double> pq = reduce(p0, q64.p);
-      std::vector<double> alpha(R, 0.0);
-      for (int r = 0; r < R; ++r) {
-        if (!live[r]) continue;
-        OVL_REQUIRE(std::isfinite(pq[r]), OVL_E_NAN, "NaN or Inf in a multi-mass CG iterate");
-        OVL_REQUIRE(pq[r] > 0.0, OVL_E_BREAKDOWN, "multi-mass CG breakdown: p^dag A p <= 0");
-        alpha[r] = rr[r] / pq[r];
-      }
-      // shifted coefficients
-      std::vector<std::vector<double>> zn = zeta, aj(nm, std::vector<double>(R, 0.0));
-      for (int j = 0; j < nm; ++j)
-        for (int r = 0; r < R; ++r) {
-          if (!live[r]) continue;
-          if (j == base) {
-            zn[j][r] = 1.0;
-            aj[j][r] = alpha[r];
-            continue;
-          }
-          const double d = sigma[j] - sigma[base];
-          const double z = zeta[j][r], zp = zeta_p[j][r];
-          const double den = alpha[r] * beta_p[r] * (zp - z) + zp * alpha_p[r] * (1.0 + d * alpha[r]);
-          zn[j][r] = (den != 0.0) ? z * zp * alpha_p[r] / den : 0.0;
-          aj[j][r] = (z != 0.0) ? alpha[r] * zn[j][r] / z : 0.0;
-        }
-      // y_j += alpha_j p_j (active shifts only)
-      for (int j = 0; j < nm; ++j) {
-        std::vector<double> a(R, 0.0);
-        for (int r = 0; r < R; ++r) a[r] = act[j][r] ? aj[j][r] : 0.0;
-        upload(a, ones, zeros, zeros);
-        blas_axpby(OVL_F64, vec(pj.p, j), A0, OVL_F64, vec(yj.p, j), A1, N, R, s);
-      }
+      blas_dot(OVL_F64, n16, p0, q64.p, R, v64, dM->dot, s);
+      hipLaunchKernelGGL(mm_alpha_kernel, dim3(1), dim3(64), 0, s, R, nm, base, dM);
       // r -= alpha q
-      std::vector<double> ma(R);
-      for (int r = 0; r < R; ++r) ma[r] = -alpha[r];
-      upload(ma, ones, zeros, zeros);
-      blas_axpby(OVL_F64, q64.p, A0, OVL_F64, r64.p, A1, N, R, s);
-      const std::vector<double> rrn = reduce(r64.p, nullptr);
-      std::vector<double> beta(R, 0.0);
-      for (int r = 0; r < R; ++r) {
-        if (!live[r]) continue;
-        OVL_REQUIRE(std::isfinite(rrn[r]), OVL_E_NAN, "NaN or Inf in a multi-mass CG iterate");
-        beta[r] = rrn[r] / rr[r];
-      }
-      // p_j = zeta_j r + beta_j p_j (frozen for finished shifts)
-      for (int j = 0; j < nm; ++j) {
-        std::vector<double> zc(R, 0.0), bc(R, 1.0);
-        for (int r = 0; r < R; ++r) {
-          if (!live[r] || !act[j][r]) continue;
-          const double ratio = (zeta[j][r] != 0.0) ? zn[j][r] / zeta[j][r] : 0.0;
-          zc[r] = zn[j][r];
-          bc[r] = beta[r] * ratio * ratio;
-        }
-        upload(zc, bc, zeros, zeros);
-        blas_axpby(OVL_F64, r64.p, A0, OVL_F64, vec(pj.p, j), A1, N, R, s);
-      }
+      blas_axpby(OVL_F64, q64.p, dM->malpha, OVL_F64, r64.p, dM->one, N, R, s);
+      blas_norm2(OVL_F64, n16, r64.p, R, v64, dM->nrm, s);
+      hipLaunchKernelGGL(mm_beta_kernel, dim3(1), dim3(64), 0, s, R, nm, dM);
+      // y_j += alpha_j p_j;  p_j = zeta_j r + beta_j p_j
+      hipLaunchKernelGGL(mm_update_kernel, dim3((n16 + 255) / 256, R), dim3(256), 0, s, n16, R, nm,
+                         static_cast<const double2*>(r64.p), static_cast<double2*>(yj.p),
+                         static_cast<double2*>(pj.p), dM);
+      OVL_HIP(hipGetLastError());
       ++its;
-      for (int r = 0; r < R; ++r) {
-        if (!live[r]) continue;
-        for (int j = 0; j < nm; ++j) {
-          zeta_p[j][r] = zeta[j][r];
-          zeta[j][r] = zn[j][r];
-          // residual of shift j is zeta_j r
-          if (act[j][r] && std::fabs(zeta[j][r]) * std::sqrt(rrn[r]) <= rel * std::sqrt(bn2[r])) act[j][r] = 0;
-        }
-        alpha_p[r] = alpha[r];
-        beta_p[r] = beta[r];
-        rr[r] = rrn[r];
-      }
       if (log_on() && its % 100 == 0) fprintf(stderr, "[ovl multimass] iteration %d\n", its);
     }
     // x_j = D(m_j)^dag y_j / c_j in FP64
