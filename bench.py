@@ -81,6 +81,8 @@ def parse():
     ap.add_argument("--cpu-data", type=str, default="", help=argparse.SUPPRESS)
     ap.add_argument("--cpu-seed", type=int, default=0, help=argparse.SUPPRESS)
     ap.add_argument("--no-c2", action="store_true", help="skip the 16^3x32 block (C2)")
+    ap.add_argument("--rational-n", type=int, default=18,
+                    help="order of the rational sign compared with the polynomial (0 skips the comparison)")
     ap.add_argument("--defl-ell", type=int, default=16,
                     help="16^3x32 block: chiral-sector eigenvectors for the deflated CG (eq. 9); 0 skips it")
     ap.add_argument("--shape", type=str, default="",
@@ -515,6 +517,40 @@ def deflation_block(ovl, g, gauge, rho, m, sgn, sgn_in, lm, b64, ell, plain):
     return rec
 
 
+def sign_comparison(ovl, g, gauge, rho, lams, lam_max, V, lm, sgn, args):
+    """The paper's comparison of sign approximations (Sec. V): one FP64
+    sign(H_w) application on a Gaussian vector with the same projected low
+    modes, by the polynomial (Clenshaw) and by the rational function of order
+    rational_n (multi-shift CG and double pass, Krylov tolerance 1e-10);
+    time, H_w applications and the difference between the results."""
+    import numpy as np
+    import torch
+
+    import synth_inputs as si
+
+    dev = torch.device("cuda:0")
+    v64 = g.spinor_bytes(ovl.OVL_F64)
+    psi = torch.empty(v64, dtype=torch.uint8, device=dev)
+    ovl.ovl_pack_spinor(g, torch.from_numpy(si.gaussian_spinor(g.dims, 77)[None]).to(dev), psi, ovl.OVL_F64, 1, None)
+    ref = torch.empty_like(psi)
+    t_poly = _event_time(lambda: ovl.ovl_sign_apply(ref, psi, gauge, rho, sgn, lm, ovl.OVL_F64, 1, None), 3)
+    rat = ovl.Rational(abs(lams[-1]), lam_max, args.rational_n)
+    out = {"workload": "one FP64 vector, %s lattice, %d projected modes" % ("x".join(map(str, g.dims)), len(lams)),
+           "polynomial": {"n": sgn.n, "delta": sgn.delta, "seconds": round(t_poly, 4), "hw_applies": 2 * sgn.n + 1},
+           "rational_n": rat.n, "rational_delta": rat.delta}
+    pn = torch.linalg.vector_norm(ref.view(torch.float64)).item()
+    for name, method in (("multishift_cg", 0), ("double_pass", 1)):
+        res = torch.empty_like(psi)
+        st = ovl.RationalStats()
+        rc = ovl.ovl_rational_sign_apply(res, psi, gauge, rho, rat, lm, method, 1e-10, 5000, ctypes.byref(st), None)
+        diff = torch.linalg.vector_norm(res.view(torch.float64) - ref.view(torch.float64)).item() / pn
+        out[name] = {"rc": rc, "seconds": round(st.seconds, 4), "krylov_steps": st.iterations,
+                     "hw_applies": st.hw_applies, "rel_diff_vs_polynomial": diff,
+                     "time_vs_polynomial": round(st.seconds / t_poly, 2)}
+        log("sign comparison %s: %s" % (name, out[name]))
+    return out
+
+
 def _event_time(fn, reps):
     """Seconds per call of fn, timed with HIP events on torch's current stream
     (the stream the library's kernels are launched on) after one warm-up."""
@@ -777,6 +813,11 @@ def main():
             cg["speedup_vs_plain_f64_m%.2f" % m0] = round(t_den / cg[key]["seconds"], 2)
             cg["speedup_vs_plain_f64_separate_m%.2f" % m0] = round(t_sep / cg[key]["seconds"], 2)
 
+    sign_cmp = None
+    if args.rational_n > 0:
+        log("sign comparison: polynomial vs rational (multi-shift CG, double pass)")
+        sign_cmp = sign_comparison(ovl, g, gauge, rho, lams, lam_max, V, lm, sgn, args)
+
     c2 = None
     if not args.no_c2:
         log("C2 block (16x16x16x32)")
@@ -828,6 +869,7 @@ def main():
         "dslash": dslash,
         "cg": cg,
         "c2_16x16x16x32": c2,
+        "sign_comparison": sign_cmp,
         "memory": memory,
     }
     print(json.dumps(out), flush=True)

@@ -227,6 +227,40 @@ int ovl_sign_apply(void* out, const void* in, const ovl_gauge* u, double rho, co
 int ovl_overlap_apply(void* out, const void* in, const ovl_gauge* u, double rho, double m, const ovl_sign* sign,
                       const ovl_lowmodes* lowmodes, int dagger, ovl_prec prec, int nrhs, ovl_stream_t s);
 
+/* ----------------------------------------------- rational sign (comparison)
+ * The rational alternative to the polynomial (eq. 4-5, Sec. V eq. 12):
+ *   sign(H_w) psi ~ sum_i sign(lambda_i)(eta_i^dag psi) eta_i + Q P(Q^2) psi_h,
+ *   P(y) = sum_{l=1}^{n} b_l / (y + c_l),
+ * P the optimal (Zolotarev, closed form) approximation of y^{-1/2} of type
+ * (n-1, n) on [eps, 1], eps = (lam_lo / lam_max)^2.
+ * ovl_rational_create: 1 <= n <= 32; the handle holds b, c and the measured
+ *   delta = max |1 - sqrt(y) P(y)| (eq. 4).  Host only.
+ * ovl_rational_coeffs: copies b[0..n), c[0..n) (cap = buffer length) and,
+ *   if non-NULL, eps and delta; returns n (or an error code < 0).
+ * ovl_rational_sign_apply: out = sign(H_w) in for one FP64 spinor with the
+ *   low modes (optional) projected exactly and P(Q^2) psi_h evaluated by
+ *   method 0: multi-shift CG (single pass; every (Q^2 + c_l) x_l = psi_h
+ *             to ||residual_l|| <= tol ||psi_h||; 2n + 3 vectors), or
+ *   method 1: double pass (Lanczos on Q^2 until the estimated truncation
+ *             error of y = P(T_k) e_1 - beta_k |y_k| / (1 - |y_k/y_{k-1}|)
+ *             - is <= tol |y_1|, then the Lanczos vectors regenerated and
+ *             summed; 7 vectors).
+ *   maxiter bounds the Krylov steps (OVL_W_NOT_CONVERGED past it).
+ *   stats: Krylov steps, H_w applications, seconds.  Synchronises s.
+ */
+typedef struct ovl_rational ovl_rational;
+typedef struct {
+  int iterations;     /* multi-shift CG steps, or Lanczos steps per pass */
+  int64_t hw_applies; /* vector applications of H_w                     */
+  double seconds;
+} ovl_rational_stats;
+int ovl_rational_create(double lam_lo, double lam_max, int n, ovl_rational** out);
+int ovl_rational_destroy(ovl_rational* r);
+int ovl_rational_coeffs(const ovl_rational* r, double* b, double* c, int cap, double* eps, double* delta);
+int ovl_rational_sign_apply(void* out, const void* in, const ovl_gauge* u, double rho, const ovl_rational* r,
+                            const ovl_lowmodes* lowmodes, int method, double tol, int maxiter,
+                            ovl_rational_stats* stats, ovl_stream_t s);
+
 /* ------------------------------------------------------------------ solvers
  * ovl_cg_solve: solves D(m) x = b for nrhs <= 12 FP64 right-hand sides
  *   (library layout, batch) by CG on D(m) D(m)^dag with x = D(m)^dag y, so

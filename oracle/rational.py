@@ -29,9 +29,11 @@ Readings (the paper cites these methods without restating them):
   from the base recurrence through the zeta_i polynomials.  The base system
   is the smallest shift (the worst conditioned); a shifted system stops
   updating once its own residual zeta_i r meets the tolerance.
-* Double pass: Lanczos with full FP64 three-term recurrence (no
-  re-orthogonalisation) until the coefficient vector P(T_k) e_1 changes by
-  less than tol in its last component, then the same recurrence again.
+* Double pass: Lanczos with the plain FP64 three-term recurrence (no
+  re-orthogonalisation) until the estimated truncation error of
+  y = P(T_k) e_1 - the coupling beta_k |y_k| to the next vector, summed as a
+  geometric series with the observed decay of |y_k| - is below tol |y_1|,
+  then the same recurrence again.
 """
 from __future__ import annotations
 
@@ -179,13 +181,20 @@ def tridiag_rational_e1(alphas, betas, r: RationalSign) -> np.ndarray:
     return sum(bi * np.linalg.solve(T + ci * np.eye(k), e1) for bi, ci in zip(r.b, r.c))
 
 
+def _tail(beta, y):
+    """Estimated size of everything the truncation at k drops: the coupling
+    beta_k |y_k| to the next Lanczos vector, summed as a geometric series
+    with the observed decay q = |y_k / y_{k-1}| of the coefficients."""
+    q = abs(y[-1]) / max(abs(y[-2]), 1e-300)
+    return beta * abs(y[-1]) / max(1.0 - q, 1e-3)
+
+
 def double_pass(apply_A, psi, r: RationalSign, tol: float = 1e-12, kmax: int = 5000):
     """P(A) psi ~ ||psi|| V_k P(T_k) e_1 in two passes.  Pass 1 runs the
     Lanczos recurrence from v_1 = psi / ||psi|| and stops at the first k
-    where beta_k |(P(T_k) e_1)_k|, the size of the neglected coupling, is
-    below tol |(P(T_k) e_1)_1| (or the Krylov space is exhausted); pass 2
-    reruns the same recurrence to regenerate v_1..v_k and sums y_j v_j.
-    Returns (out, k)."""
+    where the estimated tail (`_tail`) is below tol |(P(T_k) e_1)_1| (or the
+    Krylov space is exhausted); pass 2 reruns the same recurrence to
+    regenerate v_1..v_k and sums y_j v_j.  Returns (out, k)."""
     psi = np.asarray(psi).astype(np.complex128)
     nrm = np.linalg.norm(psi)
     # pass 1: T_k only
@@ -202,7 +211,7 @@ def double_pass(apply_A, psi, r: RationalSign, tol: float = 1e-12, kmax: int = 5
         alphas.append(a)
         betas.append(beta)
         y = tridiag_rational_e1(np.array(alphas), np.array(betas), r)
-        if beta * abs(y[-1]) <= tol * abs(y[0]) or beta == 0.0:
+        if beta == 0.0 or (len(y) >= 2 and _tail(beta, y) <= tol * abs(y[0])):
             break
         v_prev, v = v, w / beta
     k = len(alphas)

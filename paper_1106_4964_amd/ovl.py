@@ -151,6 +151,10 @@ _SIGS = {
     "ovl_lowmodes_project_noalloc": (P, P, P, P, I, I, ST),
     "ovl_sign_apply": (P, P, P, D, P, P, I, I, ST),
     "ovl_overlap_apply": (P, P, P, D, D, P, P, I, I, I, ST),
+    "ovl_rational_create": (D, D, I, P),
+    "ovl_rational_destroy": (P,),
+    "ovl_rational_coeffs": (P, P, P, I, P, P),
+    "ovl_rational_sign_apply": (P, P, P, D, P, P, I, D, I, P, ST),
     "ovl_cg_solve": (P, P, I, P, D, D, P, P, D, I, P, P, ST),
     "ovl_cg_multimass": (P, P, I, P, D, P, I, P, P, D, I, P, P, ST),
     "ovl_propagator": (P, P, P, D, P, P, I, I, ST),
@@ -340,6 +344,36 @@ class Sign:
             return
         if getattr(self, "handle", None) is not None and self.handle.value:
             _lib.ovl_sign_destroy(self.handle)
+            self.handle = None
+
+
+class RationalStats(ctypes.Structure):
+    _fields_ = [
+        ("iterations", ctypes.c_int),
+        ("hw_applies", ctypes.c_int64),
+        ("seconds", ctypes.c_double),
+    ]
+
+
+class Rational:
+    """Zolotarev rational approximation of y^{-1/2} on [eps, 1] (host handle)."""
+
+    def __init__(self, lam_lo, lam_max, n):
+        h = ctypes.c_void_p()
+        ovl_rational_create(float(lam_lo), float(lam_max), int(n), ctypes.byref(h))
+        self.handle = h
+        self.lam_max = float(lam_max)
+        self.n = int(n)
+        b, c = np.zeros(self.n), np.zeros(self.n)
+        eps, dl = ctypes.c_double(), ctypes.c_double()
+        ovl_rational_coeffs(self.handle, b, c, self.n, ctypes.byref(eps), ctypes.byref(dl))
+        self.b, self.c, self.eps, self.delta = b, c, eps.value, dl.value
+
+    def __del__(self, _lib=lib, _exiting=sys.is_finalizing):
+        if _exiting():
+            return
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            _lib.ovl_rational_destroy(self.handle)
             self.handle = None
 
 

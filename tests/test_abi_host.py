@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -92,3 +93,22 @@ def test_host_heev_against_numpy(n):
     assert np.max(np.abs(w - wn)) < 1e-12 * max(1.0, np.max(np.abs(wn)))
     assert np.max(np.abs(h @ V - V * w)) < 1e-11 * max(1.0, np.max(np.abs(wn)))
     assert np.max(np.abs(V.conj().T @ V - np.eye(n))) < 1e-13
+
+
+@pytest.mark.parametrize("n,lo,hi", [(6, 0.2, 1.0), (8, 0.44, 6.3), (12, 0.05, 6.5)])
+def test_rational_coefficients_match_the_oracle(n, lo, hi):
+    """The library's Zolotarev coefficients (its own AGM elliptic functions)
+    equal the oracle's (scipy's), and its measured delta matches (cases
+    with delta far above rounding)."""
+    from oracle import rational as ra
+    from paper_1106_4964_amd import ovl
+
+    r = ovl.Rational(lo, hi, n)
+    o = ra.make_rational(lo, hi, n)
+    assert np.max(np.abs(r.c / o.c - 1.0)) < 1e-10
+    assert np.max(np.abs(r.b / o.b - 1.0)) < 1e-9
+    assert abs(r.delta / ra.measure_delta(o) - 1.0) < 1e-3
+    with pytest.raises(ovl.OvlError):
+        ovl.Rational(lo, hi, 0)
+    with pytest.raises(ovl.OvlError):
+        ovl.Rational(hi, lo, 4)
