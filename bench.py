@@ -46,6 +46,14 @@ PROFILED_TRAFFIC = {
     (0, (2, 128, 0, 0, 0)): 3094016000,
     (3, (2, 256, 0, 0, 0)): 4072608000,
     (0, (2, 256, 0, 0, 0)): 3037061120,
+    (3, (2, 128, 0, 0, 4)): 3638409216,
+    (0, (2, 128, 0, 0, 4)): 2811045888,
+    (3, (2, 128, 0, 0, 8)): 3599534080,
+    (0, (2, 128, 0, 0, 8)): 2698047488,
+    (3, (2, 256, 0, 0, 4)): 3534860288,
+    (0, (2, 256, 0, 0, 4)): 2486437888,
+    (3, (2, 256, 0, 0, 8)): 3575134208,
+    (0, (2, 256, 0, 0, 8)): 2627336192,
 }
 
 
