@@ -57,6 +57,9 @@ PROFILED_TRAFFIC = {
 }
 
 
+LAST_EIG = {}  # statistics of the latest spectral set-up's eigensolver
+
+
 def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
@@ -278,6 +281,8 @@ def spectral_setup(ovl, g, gauge, dims, rho, ell, delta, seed_base, tol=1e-12):
     rc = ovl.ovl_hw_eigs(gauge, rho, ell, m, V, lams, lam_max, tol, 60, 40, ctypes.byref(est), None)
     log("eigensolver rc %d: %d passes, %d H_w applies, max residual %.2e, %.1f s, |lambda_l| = %.4f"
         % (rc, est.iterations, est.hw_applies, est.max_residual, est.seconds, abs(lams[-1])))
+    LAST_EIG.update(degree=40, passes=est.iterations, hw_applies=est.hw_applies, seconds=round(est.seconds, 2),
+                    max_residual=est.max_residual)
     Vk = V[: ell * g.spinor_bytes(ovl.OVL_F64)]
     lm = ovl.LowModes(g, Vk, lams)
     sgn = ovl.Sign(abs(lams[-1]), lam_max, delta=delta)
@@ -411,6 +416,7 @@ def c2_block(ovl, args):
     FP64 / FP32 / F16 storage: stencil GB/s and D(m) applies/s on one vector,
     and CG at m = 0.01 on one point source to an FP64 true residual of 1e-10
     (plain FP64, and mixed with an FP32 or F16 inner solve)."""
+    import numpy as np
     import torch
 
     import synth_inputs as si
@@ -424,6 +430,7 @@ def c2_block(ovl, args):
     t0 = time.perf_counter()
     lam_max, lams, V, lm, sgn = spectral_setup(ovl, g, gauge, dims, rho, ell, 1e-10, 2000)
     t_setup = time.perf_counter() - t0
+    setup_eig = dict(LAST_EIG)
     sgn_in = ovl.Sign(abs(lams[-1]), lam_max, delta=1e-3)
     b64 = torch.empty(g.spinor_bytes(ovl.OVL_F64), dtype=torch.uint8, device=dev)
     ovl.ovl_pack_spinor(g, torch.from_numpy(si.point_source(dims, 0, 0)[None]).to(dev), b64, ovl.OVL_F64, 1, None)
@@ -455,6 +462,22 @@ def c2_block(ovl, args):
         out[name] = rec
     out["cg_speedup_f16_vs_f64"] = round(out["f64"]["cg"]["seconds"] / out["f16"]["cg"]["seconds"], 2)
     out["cg_speedup_f32_vs_f64"] = round(out["f64"]["cg"]["seconds"] / out["f32"]["cg"]["seconds"], 2)
+    # the paper's eigensolver filter degree (a Chebyshev polynomial T_100 of
+    # H_w^2) against the default degree 40 of the set-up above
+    m_basis = ell + max(12, ell // 4)
+    Vt = torch.empty(g.spinor_bytes(ovl.OVL_F64, m_basis), dtype=torch.uint8, device=dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(2000)
+    Vt.view(torch.float64).normal_(generator=gen)
+    lt = np.zeros(ell)
+    est = ovl.EigStats()
+    rc = ovl.ovl_hw_eigs(gauge, rho, ell, m_basis, Vt, lt, lam_max, 1e-12, 60, 100, ctypes.byref(est), None)
+    out["eigensolver_T100"] = {"rc": rc, "degree": 100, "passes": est.iterations, "hw_applies": est.hw_applies,
+                               "seconds": round(est.seconds, 2), "max_residual": est.max_residual,
+                               "max_abs_eigenvalue_diff_vs_degree40": float(np.max(np.abs(np.abs(lt) - np.abs(lams)))),
+                               "degree40": setup_eig}
+    log("C2 eigensolver with T_100: %s" % out["eigensolver_T100"])
+    del Vt
     # adaptive precision (Sec. V): the same F16-inner solve with coarser
     # inner signs allowed in the cycles that need less than inner_tol
     relax = [ovl.Sign(abs(lams[-1]), lam_max, delta=d) for d in (1e-2, 1e-1)]
