@@ -342,9 +342,9 @@ __device__ inline void epilogue(const StencilArgs& A, size_t off, int p, int h, 
   SpinorIO<P>::store_nt(static_cast<char*>(A.out) + off, p, h, A.g.Nh, acc);
 }
 
-// Output site (parity p, half index h) of this thread; false past the end.
-__device__ inline bool stencil_site(const StencilArgs& A, int& p, int& h) {
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+// Site i of logical block lb, for blocks of bs sites: parity p and half
+// index h; false past the end.
+__device__ inline bool tile_site(const StencilArgs& A, int lb, int bs, int i, int& p, int& h) {
   int hb;
   if (A.npar == 2) {
     p = lb & 1;
@@ -358,24 +358,30 @@ __device__ inline bool stencil_site(const StencilArgs& A, int& p, int& h) {
     // (x, y, z) half-slice at t, then the same slab at t + 1, ..., before the
     // next slab, so a site's t-neighbours are read 2 Z Lx Ly / 2 half-sites
     // apart in launch order instead of Lx Ly Lz (a slice of the whole lattice)
-    const int Z = A.tmaj, bps = (Z * A.g.sz + static_cast<int>(blockDim.x) - 1) / static_cast<int>(blockDim.x);
+    const int Z = A.tmaj, bps = (Z * A.g.sz + bs - 1) / bs;
     const int per_slab = bps * A.g.Lt;
     const int slab = hb / per_slab, r = hb - slab * per_slab;
     const int t = r / bps, j = r - t * bps;
     const int z0 = slab * Z;
     const int len = min(Z, A.g.Lz - z0) * A.g.sz;  // the last slab may be thinner
-    const int hl = j * static_cast<int>(blockDim.x) + static_cast<int>(threadIdx.x);
+    const int hl = j * bs + i;
     h = t * A.g.st + z0 * A.g.sz + hl;
     return hl < len;
   }
   if (A.tmaj) {
     const int tile = hb / A.g.Lt, t = hb - tile * A.g.Lt;
-    const int hl = tile * blockDim.x + threadIdx.x;
+    const int hl = tile * bs + i;
     h = t * A.g.st + hl;
     return hl < A.g.st;
   }
-  h = hb * blockDim.x + threadIdx.x;
+  h = hb * bs + i;
   return h < A.g.Nh;
+}
+
+// Output site (parity p, half index h) of this thread; false past the end.
+__device__ inline bool stencil_site(const StencilArgs& A, int& p, int& h) {
+  return tile_site(A, xcd_remap(blockIdx.x, gridDim.x), static_cast<int>(blockDim.x), static_cast<int>(threadIdx.x),
+                   p, h);
 }
 
 // One thread: one output site and KR consecutive vectors of the batch, so
