@@ -94,6 +94,8 @@ def parse():
     ap.add_argument("--no-c2", action="store_true", help="skip the 16^3x32 block (C2)")
     ap.add_argument("--rational-n", type=int, default=18,
                     help="order of the rational sign compared with the polynomial (0 skips the comparison)")
+    ap.add_argument("--deflate", type=int, default=0,
+                    help="chiral-sector eigenvectors for a deflated 12-rhs CG at the main workload (0 = skip)")
     ap.add_argument("--defl-ell", type=int, default=16,
                     help="16^3x32 block: chiral-sector eigenvectors for the deflated CG (eq. 9); 0 skips it")
     ap.add_argument("--shape", type=str, default="",
@@ -637,6 +639,7 @@ def main():
         learned_mode(args, dims)
         return
     os.environ.setdefault("OVL_LOG", "1")  # solver progress lines on stderr
+    import ctypes
     import tempfile
 
     import numpy as np
@@ -793,10 +796,12 @@ def main():
             log("inner sign: n = %d (delta %.1e)" % (sgn_in.n, sgn_in.delta))
             cg["inner_sign_order"] = sgn_in.n
 
-        def solve(p, nrhs, m, graph, inner_tol, inner_sign=None, maxiter=20000):
+        def solve(p, nrhs, m, graph, inner_tol, inner_sign=None, maxiter=20000, deflation=None):
             x = torch.zeros(g.spinor_bytes(ovl.OVL_F64, nrhs), dtype=torch.uint8, device=dev)
             opts = ovl.SolveOpts(p, inner_tol, graph, 1, 60, None, None, 0,
                                  inner_sign.handle.value if inner_sign is not None else None)
+            if deflation is not None:
+                opts.deflation = deflation.handle.value
             st = ovl.SolveStats()
             rc = ovl.ovl_cg_solve(x, b64[: g.spinor_bytes(ovl.OVL_F64, nrhs)], nrhs, gauge, rho, m, sgn, lm,
                                   1e-10, maxiter, opts, st, None)
@@ -809,6 +814,33 @@ def main():
             log("CG mixed m=%.2f: %s" % (m, r_mixed))
             cg["mixed_%s_12rhs_m%.2f" % (args.prec, m)] = r_mixed
         m0 = masses[0]
+        if args.deflate > 0:
+            # eq. 9 at this workload: 2 x deflate eigenpairs of D from one
+            # chiral sector (FP64 sign with the projected modes), then the
+            # same mixed 12-rhs solve with deflation in every FP64 cycle
+            ellp = args.deflate
+            Vd = torch.empty(g.spinor_bytes(ovl.OVL_F64, 2 * ellp), dtype=torch.uint8, device=dev)
+            ovl.ovl_pack_spinor(g, torch.from_numpy(si.gaussian_spinor(dims, 7)[None]).to(dev), Vd, ovl.OVL_F64, 1,
+                                None)
+            dd = np.zeros(4 * ellp)
+            nout = ctypes.c_int()
+            est = ovl.EigStats()
+            Kb = min(512, max(2 * ellp + 16, ellp + 48))
+            erc = ovl.ovl_overlap_eigs(gauge, rho, sgn, lm, +1, ellp, Kb, Vd, dd, ctypes.byref(nout), 1e-9, 60,
+                                       ctypes.byref(est), None)
+            dc = dd[: 2 * nout.value].view(np.complex128)
+            defl = ovl.Deflation(g, Vd, dc)
+            r_defl = solve(prec, R, m0, args.graph_chunk, args.inner_tol, sgn_in, deflation=defl)
+            base = cg["mixed_%s_12rhs_m%.2f" % (args.prec, m0)]
+            cg["deflated_%s_12rhs_m%.2f" % (args.prec, m0)] = {
+                "sector_vectors": ellp, "pairs_of_D": nout.value, "eig_rc": erc, "eig_seconds": round(est.seconds, 1),
+                "eig_restart_cycles": est.iterations, "eig_dslash_applies": est.hw_applies,
+                "eig_max_residual": est.max_residual, "abs_d_min": float(np.abs(dc[0])),
+                "abs_d_max": float(np.abs(dc[-1])), "cg": r_defl,
+                "iteration_ratio": round(r_defl["iterations"] / max(1, base["iterations"]), 3),
+                "time_ratio": round(r_defl["seconds"] / base["seconds"], 3)}
+            log("CG deflated m=%.2f: %s" % (m0, cg["deflated_%s_12rhs_m%.2f" % (args.prec, m0)]))
+            del defl, Vd
         if args.fp64_cg_rhs > 0:
             nfp = min(R, args.fp64_cg_rhs)
             r64 = solve(ovl.OVL_F64, nfp, m0, 0, 0.0)
