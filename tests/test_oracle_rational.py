@@ -38,11 +38,11 @@ def test_zolotarev_error_equioscillates(n, lo):
 
 def test_rational_converges_faster_than_the_polynomial():
     """At eps = 5e-3 the rational function of 12 terms is more accurate than
-    the degree-150 Chebyshev polynomial; delta falls with n."""
+    the optimal polynomial of order 150; delta falls with n."""
     lo = math.sqrt(5e-3)
     deltas = [ra.measure_delta(ra.make_rational(lo, 1.0, n)) for n in (4, 8, 12)]
     assert deltas[0] > deltas[1] > deltas[2]
-    poly_delta = sign.measure_delta(sign.chebyshev_coefficients(5e-3, 150), 5e-3, 100_000)
+    poly_delta = sign.measure_delta(sign.minimax_coefficients(5e-3, 150), 5e-3, 100_000)
     assert deltas[2] < poly_delta
 
 

@@ -41,32 +41,81 @@ def test_chebyshev_eval_agrees_with_numpy_chebval():
     assert np.max(np.abs(sign.chebyshev_eval(c, y) - np.polynomial.chebyshev.chebval(y, c))) < 1e-12
 
 
-def test_fig2_anchor_is_a_lower_bound():
-    """Fig. 2: the optimal order-13 polynomial has delta = 0.1 at sqrt(eps) = 0.06.
-    No polynomial of that order does better, so the interpolant's delta >= 0.1
-    (allowing for the rounding in the caption), and it is within a small factor."""
+def test_fig2_anchor_optimal_polynomial():
+    """Fig. 2: the optimal order-13 polynomial at sqrt(eps) ~ 0.06 has
+    delta = 0.1 (to the caption's one digit and its "~").  The Chebyshev
+    interpolant of the same order misses it by far (~0.18)."""
     n = int(ANCH["fig2_n"])
     eps = float(ANCH["fig2_sqrt_eps"]) ** 2
-    d = sign.measure_delta(sign.chebyshev_coefficients(eps, n), eps)
-    assert 0.9 * float(ANCH["fig2_delta"]) <= d <= 2.5 * float(ANCH["fig2_delta"])
+    d = sign.measure_delta(sign.minimax_coefficients(eps, n), eps)
+    d_interp = sign.measure_delta(sign.chebyshev_coefficients(eps, n), eps)
+    assert 0.9 * float(ANCH["fig2_delta"]) <= d <= 1.15 * float(ANCH["fig2_delta"])
+    assert d_interp > 1.5 * d
 
 
-@pytest.mark.parametrize("n", [60, 120, 200])
+def _alternation(e, tol):
+    """Length of the longest sign-alternating sequence of grid points where
+    |e| is within a factor (1 - tol) of max |e|."""
+    top = np.max(np.abs(e))
+    idx = np.flatnonzero(np.abs(e) >= (1.0 - tol) * top)
+    count, last = 0, 0.0
+    for i in idx:
+        sgn = np.sign(e[i])
+        if sgn != last:
+            count += 1
+            last = sgn
+    return count
+
+
+@pytest.mark.parametrize("sq,n", [(0.06, 13), (0.1, 30), (0.0689, 60), (0.2, 8)])
+def test_optimal_polynomial_equioscillates(sq, n):
+    """Chebyshev's alternation theorem characterises the optimal P of eq. (4)
+    (weight sqrt(x) on the error of x^{-1/2}): |e| reaches its maximum with
+    alternating sign at n + 2 points at least, and no other polynomial of
+    order n does.  The interpolant does not (its error is larger near
+    x = eps), and neither would an unweighted (absolute-error) optimum."""
+    eps = sq * sq
+    x = sign.delta_grid(eps, 400_000)
+    x.sort()
+    e = sign.relative_error(sign.minimax_coefficients(eps, n), eps, x)
+    assert _alternation(e, 1e-6) >= n + 2
+    e_interp = sign.relative_error(sign.chebyshev_coefficients(eps, n), eps, x)
+    assert _alternation(e_interp, 1e-6) < n + 2
+    # an absolute-error optimum levels |x^{-1/2} - P| instead: its relative error is not level
+    c_abs = np.polynomial.chebyshev.chebfit(sign.y_of_x(x, eps), x ** -0.5, n)
+    assert _alternation(sign.relative_error(c_abs, eps, x), 1e-6) < n + 2
+
+
+@pytest.mark.parametrize("n", [40, 80, 120])
 def test_delta_follows_order_law(n):
-    """eq. (11) with A = 0.41, b = 2.1: the interpolant is within a factor 5 of it."""
+    """eq. (11) with A = 0.41, b = 2.1 (fitted to optimal polynomials): the
+    optimal delta follows it to 25%; the interpolant sits ~1.8x above."""
     A, b = float(ANCH["order_law_A"]), float(ANCH["order_law_b"])
     sq = 0.0689
-    d = sign.measure_delta(sign.chebyshev_coefficients(sq * sq, n), sq * sq)
+    d = sign.measure_delta(sign.minimax_coefficients(sq * sq, n), sq * sq)
     law = A * math.exp(-b * n * sq)
-    assert law / 5 <= d <= 5 * law
+    assert law / 1.25 <= d <= 1.25 * law
+    d_interp = sign.measure_delta(sign.chebyshev_coefficients(sq * sq, n), sq * sq)
+    assert d_interp > 1.5 * d
+
+
+def test_rounding_level_keeps_interpolant():
+    """Where the interpolant's delta is already at FP64 rounding the exchange
+    has nothing to level: the interpolant is returned unchanged."""
+    eps = 0.3 ** 2
+    c = sign.minimax_coefficients(eps, 120)
+    assert sign.measure_delta(c, eps) <= sign.ROUNDING_DELTA
+    assert np.array_equal(c, sign.chebyshev_coefficients(eps, 120))
 
 
 def test_choose_order_is_minimal():
     eps, target = 0.0689 ** 2, 1e-8
     n = sign.choose_order(eps, target)
-    assert sign.measure_delta(sign.chebyshev_coefficients(eps, n), eps) <= target
-    assert sign.measure_delta(sign.chebyshev_coefficients(eps, n - 1), eps) > target
-    assert abs(n - sign.order_law_n(eps, target)) <= 0.15 * n
+    assert sign.measure_delta(sign.minimax_coefficients(eps, n), eps) <= target
+    assert sign.measure_delta(sign.minimax_coefficients(eps, n - 1), eps) > target
+    # the optimal polynomials follow eq. (11): its order is within a few per cent
+    assert abs(n - sign.order_law_n(eps, target)) <= 0.05 * n
+    assert n < sign.interpolant_order(eps, target)
 
 
 # -- dense references at 2^4 ----------------------------------------------------
