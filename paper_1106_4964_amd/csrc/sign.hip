@@ -3,7 +3,8 @@
 //
 //   sign(H_w) psi = sum_i sign(lambda_i) (eta_i^dag psi) eta_i + Q P(Q^2) psi_h,
 //   psi_h = psi - sum_i (eta_i^dag psi) eta_i,   Q = H_w / lam_max,
-//   P(x) = sum_k c_k T_k(y),  y = (2x - 1 - eps)/(1 - eps),
+//   P(x) = sum_k c_k T_k(y),  y = (2x - 1 - eps)/(1 - eps), the optimal
+//   polynomial of order n (eq. 4; coefficients by the Remez exchange below),
 // with P(Q^2) psi_h evaluated by the Clenshaw recursion
 //   b_k = c_k psi_h + 2 Y b_{k+1} - b_{k+2},  P psi_h = c_0 psi_h + Y b_1 - b_2,
 //   Y = (2 Q^2 - 1 - eps)/(1 - eps),
@@ -44,33 +45,206 @@ std::vector<double> cheb_coeffs(double eps, int n) {
 
 // max |1 - sqrt(x) P(x)| over npts points of [eps, 1]: half uniform in x,
 // half at cos(theta) for theta uniform in [0, pi] (dense near both ends).
+// The points go through the Clenshaw recursion 16 at a time (independent
+// lanes the compiler vectorises); a NaN anywhere gives INFINITY.
 double sign_delta(const std::vector<double>& c, double eps, int npts = 400000) {
+  constexpr int B = 16;
   const int half = npts / 2, rest = npts - half;
   const double pi = 3.14159265358979323846;
-  double worst = 0.0;
-  auto eval = [&](double x) {
-    const double y = (2.0 * x - 1.0 - eps) / (1.0 - eps);
-    double b1 = 0.0, b2 = 0.0;  // Clenshaw in y
-    for (int k = static_cast<int>(c.size()) - 1; k >= 1; --k) {
-      const double b = c[k] + 2.0 * y * b1 - b2;
-      b2 = b1;
-      b1 = b;
-    }
-    const double p = c[0] + y * b1 - b2;
-    const double d = std::fabs(1.0 - std::sqrt(x) * p);
-    if (d > worst || d != d) worst = (d != d) ? INFINITY : d;
+  const int nc = static_cast<int>(c.size());
+  auto point = [&](int i) {
+    if (i < half) return half == 1 ? eps : eps + (1.0 - eps) * i / (half - 1);
+    const int j = i - half;
+    const double th = rest == 1 ? 0.0 : pi * j / (rest - 1);
+    return 0.5 * ((1.0 - eps) * std::cos(th) + 1.0 + eps);
   };
-  for (int i = 0; i < half; ++i) eval(half == 1 ? eps : eps + (1.0 - eps) * i / (half - 1));
-  for (int i = 0; i < rest; ++i) {
-    const double th = rest == 1 ? 0.0 : pi * i / (rest - 1);
-    eval(0.5 * ((1.0 - eps) * std::cos(th) + 1.0 + eps));
+  double worst = 0.0;
+  bool nan = false;
+  for (int i0 = 0; i0 < npts; i0 += B) {
+    const int cnt = std::min(B, npts - i0);
+    double x[B], y[B], b1[B], b2[B];
+    for (int l = 0; l < B; ++l) {
+      x[l] = point(i0 + std::min(l, cnt - 1));
+      y[l] = (2.0 * x[l] - 1.0 - eps) / (1.0 - eps);
+      b1[l] = 0.0;
+      b2[l] = 0.0;
+    }
+    for (int k = nc - 1; k >= 1; --k) {
+      const double ck = c[k];
+      for (int l = 0; l < B; ++l) {
+        const double b = ck + 2.0 * y[l] * b1[l] - b2[l];
+        b2[l] = b1[l];
+        b1[l] = b;
+      }
+    }
+    for (int l = 0; l < cnt; ++l) {
+      const double d = std::fabs(1.0 - std::sqrt(x[l]) * (c[0] + y[l] * b1[l] - b2[l]));
+      if (d != d) nan = true;
+      else worst = std::max(worst, d);
+    }
   }
-  return worst;
+  return nan ? INFINITY : worst;
+}
+
+// ------------------------------------------------------ optimal polynomial
+// P of order n minimising delta = max |1 - sqrt(x) P(x)| over [eps, 1] (the
+// optimal approximation of eq. 4; Fig. 2 prints delta = 0.1 at n = 13,
+// sqrt(eps) ~ 0.06).  Remez exchange on the relative error, P kept as
+// Chebyshev coefficients in y: on a reference r_0 < ... < r_{n+1} the linear
+// system sum_k c_k T_k(y(r_i)) + (-1)^i E / sqrt(r_i) = 1 / sqrt(r_i)
+// levels the error to (-1)^i E; the error then has one zero between
+// consecutive reference points (found by bisection) and the next reference
+// is the peak of |error| between consecutive zeros, the ends eps and 1
+// included (golden-section search).  The start is the Chebyshev
+// interpolant, whose error vanishes at its n+1 nodes.  Kept instead of the
+// exchange: the interpolant itself when its delta is at the level of FP64
+// rounding (<= 1e-12, nothing left to level) or the order is above 1000
+// (the dense (n+2)^2 system), and whenever the exchange ends worse.
+namespace {
+
+constexpr double kRoundingDelta = 1e-12;
+constexpr int kMinimaxMaxOrder = 1000;
+
+double cheb_value(const std::vector<double>& c, double y) {
+  double b1 = 0.0, b2 = 0.0;
+  for (int k = static_cast<int>(c.size()) - 1; k >= 1; --k) {
+    const double b = c[k] + 2.0 * y * b1 - b2;
+    b2 = b1;
+    b1 = b;
+  }
+  return c[0] + y * b1 - b2;
+}
+
+// 1 - sqrt(x) P(x)
+double rel_error(const std::vector<double>& c, double eps, double x) {
+  return 1.0 - std::sqrt(x) * cheb_value(c, (2.0 * x - 1.0 - eps) / (1.0 - eps));
+}
+
+// Solves the m x m row-major system in place (Gaussian elimination with
+// partial pivoting); false when a pivot vanishes.
+bool dense_solve(std::vector<double>& a, std::vector<double>& rhs, int m) {
+  for (int col = 0; col < m; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < m; ++r)
+      if (std::fabs(a[static_cast<size_t>(r) * m + col]) > std::fabs(a[static_cast<size_t>(piv) * m + col])) piv = r;
+    if (a[static_cast<size_t>(piv) * m + col] == 0.0) return false;
+    if (piv != col) {
+      for (int k = 0; k < m; ++k) std::swap(a[static_cast<size_t>(col) * m + k], a[static_cast<size_t>(piv) * m + k]);
+      std::swap(rhs[col], rhs[piv]);
+    }
+    const double d = a[static_cast<size_t>(col) * m + col];
+    for (int r = col + 1; r < m; ++r) {
+      const double f = a[static_cast<size_t>(r) * m + col] / d;
+      if (f == 0.0) continue;
+      for (int k = col; k < m; ++k) a[static_cast<size_t>(r) * m + k] -= f * a[static_cast<size_t>(col) * m + k];
+      rhs[r] -= f * rhs[col];
+    }
+  }
+  for (int r = m - 1; r >= 0; --r) {
+    double v = rhs[r];
+    for (int k = r + 1; k < m; ++k) v -= a[static_cast<size_t>(r) * m + k] * rhs[k];
+    rhs[r] = v / a[static_cast<size_t>(r) * m + r];
+  }
+  return true;
+}
+
+// Point of largest |error| in [a, b]: golden-section search, then the
+// better of its result and the two ends.
+double peak_of(const std::vector<double>& c, double eps, double a, double b) {
+  const double g = 0.5 * (std::sqrt(5.0) - 1.0);
+  double lo = a, hi = b;
+  for (int it = 0; it < 64; ++it) {
+    const double x1 = hi - g * (hi - lo), x2 = lo + g * (hi - lo);
+    if (std::fabs(rel_error(c, eps, x1)) > std::fabs(rel_error(c, eps, x2))) hi = x2;
+    else lo = x1;
+  }
+  double best = a, fb = std::fabs(rel_error(c, eps, a));
+  for (double x : {0.5 * (lo + hi), b}) {
+    const double f = std::fabs(rel_error(c, eps, x));
+    if (f > fb) {
+      fb = f;
+      best = x;
+    }
+  }
+  return best;
+}
+
+// A zero of the error in [a, b], the error differing in sign at the ends.
+double zero_of(const std::vector<double>& c, double eps, double a, double b) {
+  double fa = rel_error(c, eps, a);
+  for (int it = 0; it < 60; ++it) {
+    const double m = 0.5 * (a + b), fm = rel_error(c, eps, m);
+    if ((fm < 0.0) != (fa < 0.0)) {
+      b = m;
+    } else {
+      a = m;
+      fa = fm;
+    }
+  }
+  return 0.5 * (a + b);
+}
+
+}  // namespace
+
+// The optimal coefficients of order n; *delta receives their measured delta.
+std::vector<double> minimax_coeffs(double eps, int n, double* delta) {
+  const std::vector<double> c0 = cheb_coeffs(eps, n);
+  const double d0 = sign_delta(c0, eps);
+  *delta = d0;
+  if (d0 <= kRoundingDelta || n > kMinimaxMaxOrder) return c0;
+  const double pi = 3.14159265358979323846;
+  const int m = n + 2;
+  std::vector<double> edge(n + 3);
+  edge[0] = eps;
+  edge[n + 2] = 1.0;
+  for (int j = 0; j <= n; ++j)  // the interpolant's nodes, ascending in x
+    edge[n + 1 - j] = 0.5 * ((1.0 - eps) * std::cos(pi * (j + 0.5) / (n + 1)) + 1.0 + eps);
+  std::vector<double> ref(m);
+  for (int i = 0; i < m; ++i) ref[i] = peak_of(c0, eps, edge[i], edge[i + 1]);
+  std::vector<double> c = c0, a(static_cast<size_t>(m) * m), rhs(m);
+  double best_gap = INFINITY;
+  int stall = 0;
+  for (int it = 0; it < 60; ++it) {
+    for (int i = 0; i < m; ++i) {
+      const double y = (2.0 * ref[i] - 1.0 - eps) / (1.0 - eps);
+      double* row = &a[static_cast<size_t>(i) * m];
+      row[0] = 1.0;
+      if (n >= 1) row[1] = y;
+      for (int k = 2; k <= n; ++k) row[k] = 2.0 * y * row[k - 1] - row[k - 2];
+      row[n + 1] = ((i & 1) ? -1.0 : 1.0) / std::sqrt(ref[i]);
+      rhs[i] = 1.0 / std::sqrt(ref[i]);
+    }
+    if (!dense_solve(a, rhs, m)) break;
+    std::vector<double> cn(rhs.begin(), rhs.begin() + n + 1);
+    const double E = std::fabs(rhs[n + 1]);
+    if (!(E > 0.0) || !std::isfinite(E)) break;
+    c = cn;
+    edge[0] = eps;
+    edge[n + 2] = 1.0;
+    for (int i = 0; i + 1 < m; ++i) edge[i + 1] = zero_of(c, eps, ref[i], ref[i + 1]);
+    double top = 0.0;
+    for (int i = 0; i < m; ++i) {
+      ref[i] = peak_of(c, eps, edge[i], edge[i + 1]);
+      top = std::max(top, std::fabs(rel_error(c, eps, ref[i])));
+    }
+    const double gap = top / E - 1.0;
+    if (gap < 1e-10) break;
+    if (gap < 0.999 * best_gap) {
+      best_gap = gap;
+      stall = 0;
+    } else if (++stall >= 3) {
+      break;  // e is at the level of rounding: no further levelling
+    }
+  }
+  const double d = sign_delta(c, eps);
+  if (d >= d0) return c0;
+  *delta = d;
+  return c;
 }
 
 // Smallest n with measured delta <= target, searched from the order law
 // delta = 0.41 exp(-2.1 n sqrt(eps)) (eq. 11): bracket, then bisect.
-int sign_order(double eps, double target) {
+int interp_order(double eps, double target) {
   auto ok = [&](int n) { return sign_delta(cheb_coeffs(eps, n), eps) <= target; };
   int n0 = static_cast<int>(std::ceil(std::log(0.41 / target) / (2.1 * std::sqrt(eps))));
   n0 = std::max(n0, 1);
@@ -102,6 +276,24 @@ int sign_order(double eps, double target) {
     else lo = mid;
   }
   return hi;
+}
+
+// Smallest n whose optimal polynomial has measured delta <= target: the
+// optimal delta is below the interpolant's at every n and falls with n, so
+// the search starts at the interpolant's order and steps down.  Returns the
+// coefficients of that order and their measured delta.
+std::vector<double> sign_search(double eps, double target, double* delta) {
+  int n = interp_order(eps, target);
+  std::vector<double> c = minimax_coeffs(eps, n, delta);
+  while (n > 1) {
+    double d;
+    std::vector<double> lower = minimax_coeffs(eps, n - 1, &d);
+    if (d > target) break;
+    c.swap(lower);
+    *delta = d;
+    --n;
+  }
+  return c;
 }
 
 // ------------------------------------------------------------- Clenshaw
@@ -293,12 +485,13 @@ int ovl_sign_create(double lam_lo, double lam_max, double delta, int n, ovl_sign
     OVL_REQUIRE(n >= 0 && n <= 20000, OVL_E_ARG, "order out of range");
     OVL_REQUIRE(n > 0 || (delta > 0.0 && delta < 1.0), OVL_E_ARG, "need 0 < delta < 1 when n = 0");
     const double eps = (lam_lo / lam_max) * (lam_lo / lam_max);
-    const int order = n > 0 ? n : sign_order(eps, delta);
+    double measured = 0.0;
+    std::vector<double> c = n > 0 ? minimax_coeffs(eps, n, &measured) : sign_search(eps, delta, &measured);
     ovl_sign* sg = new ovl_sign;
     sg->lam_max = lam_max;
     sg->eps = eps;
-    sg->c = cheb_coeffs(eps, order);
-    sg->delta = sign_delta(sg->c, eps);
+    sg->c = std::move(c);
+    sg->delta = measured;
     *out = sg;
     return OVL_OK;
   });
