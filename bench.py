@@ -96,6 +96,8 @@ def parse():
                     help="order of the rational sign compared with the polynomial (0 skips the comparison)")
     ap.add_argument("--deflate", type=int, default=0,
                     help="chiral-sector eigenvectors for a deflated 12-rhs CG at the main workload (0 = skip)")
+    ap.add_argument("--deflate-eig", type=str, default="f32:1e-7:1e-5",
+                    help="with --deflate: comma-separated prec:sign_delta:tol of the overlap eigensolver runs")
     ap.add_argument("--defl-ell", type=int, default=16,
                     help="16^3x32 block: chiral-sector eigenvectors for the deflated CG (eq. 9); 0 skips it")
     ap.add_argument("--shape", type=str, default="",
@@ -523,7 +525,8 @@ def deflation_block(ovl, g, gauge, rho, m, sgn, sgn_in, lm, b64, ell, plain):
     nout = ctypes.c_int()
     est = ovl.EigStats()
     K = min(512, max(2 * ell + 16, ell + 48))
-    rc = ovl.ovl_overlap_eigs(gauge, rho, sgn, lm, +1, ell, K, V, d, ctypes.byref(nout), 1e-9, 40, ctypes.byref(est),
+    rc = ovl.ovl_overlap_eigs(gauge, rho, sgn, lm, ovl.OVL_F64, +1, ell, K, V, d, ctypes.byref(nout), 1e-9, 40,
+                              ctypes.byref(est),
                               None)
     dc = d[: 2 * nout.value].view(np.complex128)
     rec = {"sector_vectors": ell, "lanczos_basis": K, "pairs_of_D": nout.value, "rc": rc,
@@ -816,31 +819,38 @@ def main():
         m0 = masses[0]
         if args.deflate > 0:
             # eq. 9 at this workload: 2 x deflate eigenpairs of D from one
-            # chiral sector (FP64 sign with the projected modes), then the
-            # same mixed 12-rhs solve with deflation in every FP64 cycle
+            # chiral sector (the sector operator's sign at the given storage
+            # precision and delta, with the projected modes), then the same
+            # mixed 12-rhs solve with deflation in every FP64 cycle
             ellp = args.deflate
-            Vd = torch.empty(g.spinor_bytes(ovl.OVL_F64, 2 * ellp), dtype=torch.uint8, device=dev)
-            ovl.ovl_pack_spinor(g, torch.from_numpy(si.gaussian_spinor(dims, 7)[None]).to(dev), Vd, ovl.OVL_F64, 1,
-                                None)
-            dd = np.zeros(4 * ellp)
-            nout = ctypes.c_int()
-            est = ovl.EigStats()
-            Kb = min(512, max(2 * ellp + 16, ellp + 48))
-            erc = ovl.ovl_overlap_eigs(gauge, rho, sgn, lm, +1, ellp, Kb, Vd, dd, ctypes.byref(nout), 1e-9, 60,
-                                       ctypes.byref(est), None)
-            dc = dd[: 2 * nout.value].view(np.complex128)
-            defl = ovl.Deflation(g, Vd, dc)
-            r_defl = solve(prec, R, m0, args.graph_chunk, args.inner_tol, sgn_in, deflation=defl)
             base = cg["mixed_%s_12rhs_m%.2f" % (args.prec, m0)]
-            cg["deflated_%s_12rhs_m%.2f" % (args.prec, m0)] = {
-                "sector_vectors": ellp, "pairs_of_D": nout.value, "eig_rc": erc, "eig_seconds": round(est.seconds, 1),
-                "eig_restart_cycles": est.iterations, "eig_dslash_applies": est.hw_applies,
-                "eig_max_residual": est.max_residual, "abs_d_min": float(np.abs(dc[0])),
-                "abs_d_max": float(np.abs(dc[-1])), "cg": r_defl,
-                "iteration_ratio": round(r_defl["iterations"] / max(1, base["iterations"]), 3),
-                "time_ratio": round(r_defl["seconds"] / base["seconds"], 3)}
-            log("CG deflated m=%.2f: %s" % (m0, cg["deflated_%s_12rhs_m%.2f" % (args.prec, m0)]))
-            del defl, Vd
+            for spec in args.deflate_eig.split(","):
+                pname, sdelta, stol = spec.split(":")
+                eprec, sdelta, stol = ovl.PREC[pname], float(sdelta), float(stol)
+                sgn_eig = ovl.Sign(abs(lams[-1]), lam_max, delta=sdelta)
+                Vd = torch.empty(g.spinor_bytes(ovl.OVL_F64, 2 * ellp), dtype=torch.uint8, device=dev)
+                ovl.ovl_pack_spinor(g, torch.from_numpy(si.gaussian_spinor(dims, 7)[None]).to(dev), Vd, ovl.OVL_F64,
+                                    1, None)
+                dd = np.zeros(4 * ellp)
+                nout = ctypes.c_int()
+                est = ovl.EigStats()
+                Kb = min(512, max(2 * ellp + 16, ellp + 48))
+                erc = ovl.ovl_overlap_eigs(gauge, rho, sgn_eig, lm, eprec, +1, ellp, Kb, Vd, dd, ctypes.byref(nout),
+                                           stol, 60, ctypes.byref(est), None)
+                dc = dd[: 2 * nout.value].view(np.complex128)
+                defl = ovl.Deflation(g, Vd, dc)
+                r_defl = solve(prec, R, m0, args.graph_chunk, args.inner_tol, sgn_in, deflation=defl)
+                rec = {"sector_vectors": ellp, "eig_prec": pname, "eig_sign_n": sgn_eig.n, "eig_sign_delta": sdelta,
+                       "eig_tol": stol, "pairs_of_D": nout.value, "eig_rc": erc, "eig_seconds": round(est.seconds, 1),
+                       "eig_restart_cycles": est.iterations, "eig_dslash_applies": est.hw_applies,
+                       "eig_max_residual": est.max_residual, "abs_d_min": float(np.abs(dc[0])),
+                       "abs_d_max": float(np.abs(dc[-1])), "cg": r_defl,
+                       "iteration_ratio": round(r_defl["iterations"] / max(1, base["iterations"]), 3),
+                       "time_ratio": round(r_defl["seconds"] / base["seconds"], 3),
+                       "eig_plus_solve_vs_undeflated": round((est.seconds + r_defl["seconds"]) / base["seconds"], 3)}
+                cg["deflated_%s_12rhs_m%.2f_eig_%s" % (args.prec, m0, pname)] = rec
+                log("CG deflated m=%.2f: %s" % (m0, rec))
+                del defl, Vd
         if args.fp64_cg_rhs > 0:
             nfp = min(R, args.fp64_cg_rhs)
             r64 = solve(ovl.OVL_F64, nfp, m0, 0, 0.0)

@@ -308,7 +308,11 @@ int ovl_rational_sign_apply(void* out, const void* in, const ovl_gauge* u, doubl
  *   sum_i xi_i (xi_i^dag r) / (rho d_i + m (1 - d_i/2)) at once and the inner
  *   CG solves only for r minus its components along the xi_i, at the reduced
  *   condition number ||D|| / |d_l'|; the cycles repeat until the FP64 true
- *   residual meets tol, so approximate eigenpairs only cost extra cycles.
+ *   residual meets tol.  Approximate eigenpairs cost extra cycles as long as
+ *   their error, amplified by 1/|rho d_i + m (1 - d_i/2)|, stays below one;
+ *   when a deflated cycle ends with a larger true residual than it started
+ *   with, x goes back to its value before that cycle, the rest of the solve
+ *   runs without deflation and stats->deflation_dropped is set.
  *   opts->relax_signs (adaptive precision, Sec. V): the accuracy of the
  *   inner operator's sign is chosen per defect-correction cycle.  The first
  *   cycle uses inner_sign; each cycle's residual reduction f, run with sign
@@ -359,6 +363,9 @@ typedef struct {
   int64_t dslash_applies;               /* vector applications of D_w        */
   int fallback_used;                    /* FGCR only: CG finished the solve  */
   int harvested;                        /* pairs written to the harvest bufs */
+  int deflation_dropped;                /* CG only: a deflated cycle raised
+                                           the residual; deflation was off
+                                           for the rest of the solve        */
 } ovl_solve_stats;
 
 int ovl_cg_solve(void* x, const void* b, int nrhs, const ovl_gauge* u, double rho, double m, const ovl_sign* sign,
@@ -445,7 +452,12 @@ int ovl_host_heev(int n, const double* A, double* w, double* V);
  *   re-orthogonalisation, basis of K <= 512 chiral half-vectors, 6 complex
  *   per site) on the Hermitian
  *   K_s = s P_s sign(H_w) P_s, P_s = (1 + s gamma5)/2, s = sector (+1 or -1),
- *   each matvec one sign application with `sign` and `lowmodes`.  The ell
+ *   each matvec one sign application with `sign` and `lowmodes` at storage
+ *   precision prec (OVL_F64 as the paper does; a lower precision converts
+ *   the vector in and the result back, so the basis and the Rayleigh-Ritz
+ *   step stay FP64 while the eigenvectors are only as good as the sign
+ *   applications: ~1e-6 in FP32, enough for the deflation below; the gauge
+ *   must hold that precision's links).  The ell
  *   lowest eigenvectors v (eigenvalue k) of K_s give, with
  *   w = P_{-s} sign(H_w) v, sn = ||w|| and u = w/sn, the eigenpairs
  *   xi = (v +- i u)/sqrt(2), d = 1 + k +- i s sn of D (a real mode, sn = 0,
@@ -453,20 +465,23 @@ int ovl_host_heev(int n, const double* A, double* w, double* V);
  *   pair, negative imaginary part first; *nout receives their number.
  *   V: caller-owned device buffer of at least 2*ell FP64 spinors; V[:, 0]
  *   holds the start vector on entry (its sector-s part is used), V[:, 0..
- *   *nout) the orthonormal eigenvectors on exit.  d: host array of 4*ell
+ *   *nout) the orthonormal eigenvectors on exit (with a lower-precision
+ *   sign, orthonormal to the level of its error divided by sn).  d: host array of 4*ell
  *   doubles, (re, im) per pair.  Stops when the Ritz residuals of the ell
  *   sector vectors are <= tol or after max_iter restart cycles
  *   (OVL_W_NOT_CONVERGED); stats->max_residual is the recomputed
  *   ||K_s v - k v||, stats->hw_applies counts D_w applications.  Device
  *   workspace: (K + 2)/2 + 3 FP64 spinors.
+ *   A pair whose partner norm sn is below 1e-9 (1e-5 below FP64) is taken
+ *   for a real mode.
  * ovl_deflation_create: n eigenpairs (xi_i, d_i) of D for the deflated CG
  *   (ovl_solve_opts.deflation, eq. 9).  Xi: n orthonormal FP64 spinors,
  *   caller-owned device memory BORROWED for the handle's lifetime; d: host
  *   array of 2n doubles (copied).  OVL_E_NAN for a non-finite eigenvalue.
  */
-int ovl_overlap_eigs(const ovl_gauge* u, double rho, const ovl_sign* sign, const ovl_lowmodes* lowmodes, int sector,
-                     int ell, int K, void* V, double* d, int* nout, double tol, int max_iter, ovl_eig_stats* stats,
-                     ovl_stream_t s);
+int ovl_overlap_eigs(const ovl_gauge* u, double rho, const ovl_sign* sign, const ovl_lowmodes* lowmodes, ovl_prec prec,
+                     int sector, int ell, int K, void* V, double* d, int* nout, double tol, int max_iter,
+                     ovl_eig_stats* stats, ovl_stream_t s);
 int ovl_deflation_create(const ovl_geom* g, int n, const void* Xi, const double* d, ovl_deflation** out);
 int ovl_deflation_destroy(ovl_deflation* df);
 

@@ -92,11 +92,16 @@ using namespace ovl;
 
 extern "C" {
 
-int ovl_overlap_eigs(const ovl_gauge* u, double rho, const ovl_sign* sgn, const ovl_lowmodes* lm, int sector, int ell,
-                     int K, void* V, double* d, int* nout, double tol, int max_iter, ovl_eig_stats* stats,
-                     ovl_stream_t st) {
+int ovl_overlap_eigs(const ovl_gauge* u, double rho, const ovl_sign* sgn, const ovl_lowmodes* lm, ovl_prec prec,
+                     int sector, int ell, int K, void* V, double* d, int* nout, double tol, int max_iter,
+                     ovl_eig_stats* stats, ovl_stream_t st) {
   return guard([&] {
     OVL_REQUIRE(u && sgn && V && d && nout && stats, OVL_E_ARG, "null argument");
+    check_prec(prec);
+    {
+      int recon = 0;
+      gauge_links(u, prec, &recon);  // OVL_E_PRECISION before any work when prec's links are missing
+    }
     OVL_REQUIRE(sector == 1 || sector == -1, OVL_E_ARG, "sector must be +1 or -1");
     OVL_REQUIRE(ell >= 1 && K >= ell + 8 && K <= 512, OVL_E_ARG, "need ell >= 1 and ell + 8 <= K <= 512");
     OVL_REQUIRE(tol > 0.0 && max_iter >= 1, OVL_E_ARG, "need tol > 0 and max_iter >= 1");
@@ -112,6 +117,10 @@ int ovl_overlap_eigs(const ovl_gauge* u, double rho, const ovl_sign* sgn, const 
     const int keep = std::max(ell + 4, std::min(K - 4, ell + (K - ell) / 2));  // thick-restart size
 
     DevBuf Q(vh * (K + 1)), w(vh), t(v64), xf(v64), wf(v64);
+    // the sign applications at storage precision prec (FP32 arithmetic below
+    // FP64): the full vector is converted in and the result back to FP64
+    const size_t vp = spinor_vec_bytes(g, prec);
+    DevBuf pin(prec == OVL_F64 ? 16 : vp), pout(prec == OVL_F64 ? 16 : vp);
     DevBuf sc(sizeof(double) * 4 + sizeof(int) * 2);
     double* dsc = static_cast<double*>(sc.p);
     int* dsect = reinterpret_cast<int*>(dsc + 4);
@@ -137,11 +146,20 @@ int ovl_overlap_eigs(const ovl_gauge* u, double rho, const ovl_sign* sgn, const 
       blas_axpby(OVL_F64, x, dsc, OVL_F64, y, keep_y ? dsc + 2 : nullptr, sites, 1, s);
       OVL_HIP(hipStreamSynchronize(s));  // the host scalars are reused
     };
-    // out = eps in (FP64, full vectors), counted
+    // out = eps in (full FP64 vectors; the sign applied at precision prec), counted
     auto eps = [&](void* out, const void* in) {
-      overlap_apply(out, in, u, rho, 0.0, sgn, lm, 0, OVL_F64, 1, s);
+      if (prec == OVL_F64) {
+        overlap_apply(out, in, u, rho, 0.0, sgn, lm, 0, OVL_F64, 1, s);
+      } else {
+        blas_convert(OVL_F64, in, prec, pin.p, N, 1, s);
+        overlap_apply(pout.p, pin.p, u, rho, 0.0, sgn, lm, 0, prec, 1, s);
+        blas_convert(prec, pout.p, OVL_F64, out, N, 1, s);
+      }
       stats->hw_applies += 2 * (static_cast<int64_t>(sgn->c.size()) - 1) + 1;
     };
+    // below this partner norm a pair is taken for a real mode: FP64 rounding,
+    // or the noise of a lower-precision sign
+    const double real_mode_sn = prec == OVL_F64 ? 1e-9 : 1e-5;
     // out = K_s in = s P_s eps in, on half-vectors
     auto apply_K = [&](void* out, const void* in) {
       to_full(xf.p, in, g, sector, s);
@@ -238,7 +256,7 @@ int ovl_overlap_eigs(const ovl_gauge* u, double rho, const ovl_sign* sgn, const 
       max_res = std::max(max_res, norm(t.p, v64));
       const double sn = norm(wf.p, v64);
       const double k = std::min(1.0, std::max(-1.0, th[i]));
-      if (sn <= 1e-9) {  // real mode of chirality `sector`
+      if (sn <= real_mode_sn) {  // real mode of chirality `sector`
         OVL_HIP(hipMemcpyAsync(vat(V, v64, n), xf.p, v64, hipMemcpyDeviceToDevice, s));
         d[2 * n] = 1.0 + k;
         d[2 * n + 1] = 0.0;

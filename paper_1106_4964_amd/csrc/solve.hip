@@ -295,6 +295,13 @@ int cg_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, doub
     };
 
     const double rms_target = P == OVL_F64 ? 1.0 : std::sqrt(12.0 * S.nsites) / 8.0;
+    // eq. 9 deflation, dropped for the rest of the solve when a cycle ends
+    // with a larger true residual than it started with: the eigenpairs are
+    // then too inaccurate (1/d(m) amplifies their error instead of removing
+    // the low modes), and x goes back to its value before that cycle
+    const ovl_deflation* defl = opt.deflation;
+    WsBuf xsave(defl ? S.v64 * R : 16, s);
+    double defl_prev = INFINITY;  // worst true residual at the last cycle start
     int its = 0;
     bool chiral_failed = false;
     double prev_worst_chiral = 0.0;
@@ -331,10 +338,24 @@ int cg_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, doub
       }
       prev_worst = worst;
       if (done) break;
-      if (opt.deflation) {
+      if (defl) {
+        if (worst > defl_prev) {
+          defl = nullptr;
+          st->deflation_dropped = 1;
+          if (log_on())
+            fprintf(stderr, "[ovl cg] deflated cycle raised the residual (%.3e -> %.3e): deflation dropped\n",
+                    defl_prev, worst);
+          OVL_HIP(hipMemcpyAsync(x, xsave.p, S.v64 * R, hipMemcpyDeviceToDevice, s));
+          prev_worst = 0.0;
+          continue;  // the true residual of the restored x
+        }
+        OVL_HIP(hipMemcpyAsync(xsave.p, x, S.v64 * R, hipMemcpyDeviceToDevice, s));
+        defl_prev = worst;
+      }
+      if (defl) {
         // eq. 9: the low part of the correction at once; the inner solve is
         // left with the residual minus its components along the eigenvectors
-        deflate(opt.deflation, rho, m, x, r64.p, R, s);
+        deflate(defl, rho, m, x, r64.p, R, s);
         S.norm2(r64.p, OVL_F64, dS->rrn, dS);
         OVL_HIP(hipMemcpyAsync(rn2.data(), dS->rrn, sizeof(double) * R, hipMemcpyDeviceToHost, s));
         OVL_HIP(hipStreamSynchronize(s));

@@ -108,6 +108,7 @@ class SolveStats(ctypes.Structure):
         ("dslash_applies", ctypes.c_int64),
         ("fallback_used", ctypes.c_int),
         ("harvested", ctypes.c_int),
+        ("deflation_dropped", ctypes.c_int),
     ]
 
 
@@ -168,7 +169,7 @@ _SIGS = {
     "ovl_hw_bound": (P, D, P, I, P, P, P, ST),
     "ovl_hw_eigs": (P, D, I, I, P, P, D, D, I, I, P, ST),
     "ovl_host_heev": (I, P, P, P),
-    "ovl_overlap_eigs": (P, D, P, P, I, I, I, P, P, P, D, I, P, ST),
+    "ovl_overlap_eigs": (P, D, P, P, I, I, I, I, P, P, P, D, I, P, ST),
     "ovl_deflation_create": (P, I, P, P, P),
     "ovl_deflation_destroy": (P,),
     "ovl_fgcr_solve": (P, P, I, P, D, D, P, P, P, I, D, I, P, P, ST),

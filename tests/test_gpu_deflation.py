@@ -33,12 +33,12 @@ def c1():
     return dict(dims=dims, lat=lat, U=U, E=E, lo=float(np.min(np.abs(w))), hi=float(np.max(np.abs(w))) * 1.0001)
 
 
-def _gpu_eigs(c1, g, gauge, s, ell, K, sector=1, tol=1e-10):
+def _gpu_eigs(c1, g, gauge, s, ell, K, sector=1, tol=1e-10, prec=F64):
     V = gu.pack(g, np.stack([si.gaussian_spinor(c1["dims"], 300 + i) for i in range(2 * ell)]), F64, 2 * ell)
     d = np.zeros(4 * ell)
     nout = ctypes.c_int()
     st = ovl.EigStats()
-    rc = ovl.ovl_overlap_eigs(gauge, RHO, s, None, sector, ell, K, V, d, ctypes.byref(nout), tol, 60,
+    rc = ovl.ovl_overlap_eigs(gauge, RHO, s, None, prec, sector, ell, K, V, d, ctypes.byref(nout), tol, 60,
                               ctypes.byref(st), None)
     dc = d[: 2 * nout.value].view(np.complex128)
     return rc, V, dc, nout.value, st
@@ -89,14 +89,114 @@ def test_deflated_cg_fewer_iterations(c1, inner):
         stt = ovl.SolveStats()
         rc = ovl.ovl_cg_solve(x, b, R, gauge, RHO, m, s, None, 1e-10, 20000, opts, ctypes.byref(stt), None)
         assert rc == 0
-        out[name] = (stt.iterations, stt.restarts, x)
+        out[name] = (stt.iterations, stt.restarts, x, stt.deflation_dropped)
     print("4^4 CG m=0.01, inner %d: %d iterations plain, %d deflated (%d pairs of D)"
           % (inner, out["plain"][0], out["deflated"][0], n))
     assert out["deflated"][0] < 0.85 * out["plain"][0]
+    assert out["deflated"][3] == 0  # good pairs are never dropped
     # the deflated solution is judged by the oracle's own D(m)
     so = sign.make_sign(c1["lo"], c1["hi"], 200)
     xs = gu.unpack(g, out["deflated"][2], F64, R)
     bs = si.point_sources(c1["dims"])[:R]
+    for r in range(R):
+        res = bs[r] - sign.overlap_apply(c1["lat"], c1["U"], xs[r], RHO, m, so)
+        assert np.linalg.norm(res) / np.linalg.norm(bs[r]) <= 1.05e-10
+
+
+def test_overlap_eigs_fp32_sign(c1):
+    """The sector operator's sign applied with FP32 storage and arithmetic
+    (the Lanczos basis and Rayleigh-Ritz in FP64): the pairs of D agree with
+    the dense exact-sign ones to the FP32 level, the eigenvectors satisfy
+    D xi = d xi through the oracle's overlap to ~1e-5, and they still deflate
+    the FP64 CG (the defect correction makes up for their accuracy)."""
+    g = ovl.Geometry(c1["dims"])
+    gauge = gu.make_gauge(g, c1["U"], [(F32, 1)])
+    s = ovl.Sign(c1["lo"], c1["hi"], n=200)
+    ell = 10
+    rc, V, d, n, st = _gpu_eigs(c1, g, gauge, s, ell, 48, 1, tol=1e-5, prec=F32)
+    print("overlap eigs, FP32 sign: rc %d, %d pairs, %d restart cycles, max residual %.2e"
+          % (rc, n, st.iterations, st.max_residual))
+    assert rc == 0 and n == 2 * ell
+    assert st.max_residual < 1e-4
+    k_ref, V_ref = oe.sector_lowest_dense(c1["E"], c1["lat"].N, 1, ell)
+    apply_E = lambda v: (c1["E"] @ v.reshape(-1)).reshape(v.shape)  # noqa: E731
+    d_ref, _ = oe.overlap_pairs(apply_E, k_ref, V_ref, 1)
+    assert np.max(np.abs(d - d_ref)) < 1e-5, (d, d_ref)
+    so = sign.make_sign(c1["lo"], c1["hi"], 200)
+    Xi = gu.unpack(g, V[: n * g.spinor_bytes(F64)], F64, n)
+    for i in range(n):
+        r = sign.massless_overlap(c1["lat"], c1["U"], Xi[i], RHO, so) - d[i] * Xi[i]
+        assert np.linalg.norm(r) < 1e-4
+    # the sector vectors are FP64-orthonormal; each partner u = P_-s eps v / sn
+    # carries the sign's FP32 error divided by sn, so pairs are orthogonal to
+    # each other only to that level
+    Xf = Xi.reshape(n, -1)
+    assert np.max(np.abs(Xf.conj() @ Xf.T - np.eye(n))) < 1e-4
+    # deflation with these pairs: fewer iterations, same FP64 residual
+    defl = ovl.Deflation(g, V, d)
+    m, R = 0.01, 4
+    b = gu.pack(g, si.point_sources(c1["dims"])[:R], F64, R)
+    its = {}
+    for name, df in (("plain", None), ("deflated", defl)):
+        x = torch.zeros(g.spinor_bytes(F64, R), dtype=torch.uint8, device=gu.DEV)
+        opts = ovl.SolveOpts(F32, 1e-3, 0, 1, 60)
+        opts.deflation = df.handle.value if df is not None else None
+        stt = ovl.SolveStats()
+        assert ovl.ovl_cg_solve(x, b, R, gauge, RHO, m, s, None, 1e-10, 20000, opts, ctypes.byref(stt), None) == 0
+        its[name] = stt.iterations
+        if df is not None:
+            xs = gu.unpack(g, x, F64, R)
+            bs = si.point_sources(c1["dims"])[:R]
+            for r in range(R):
+                res = bs[r] - sign.overlap_apply(c1["lat"], c1["U"], xs[r], RHO, m, so)
+                assert np.linalg.norm(res) / np.linalg.norm(bs[r]) <= 1.05e-10
+    print("4^4 CG m=0.01, FP32 inner: %d iterations plain, %d deflated with FP32-sign pairs" % (its["plain"],
+                                                                                               its["deflated"]))
+    assert its["deflated"] < 0.85 * its["plain"]
+
+
+def test_overlap_eigs_needs_the_precisions_links(c1):
+    """A storage precision whose links the gauge field does not hold is an
+    error, not a silent fallback."""
+    g = ovl.Geometry(c1["dims"])
+    gauge = gu.make_gauge(g, c1["U"])  # FP64 links only
+    s = ovl.Sign(c1["lo"], c1["hi"], n=50)
+    with pytest.raises(ovl.OvlError):
+        _gpu_eigs(c1, g, gauge, s, 4, 24, 1, tol=1e-5, prec=ovl.OVL_F16)
+
+
+def test_wrong_eigenpairs_are_dropped(c1):
+    """A deflation whose pairs are not eigenpairs of D (random orthonormal
+    vectors, |d| = 1e-3): eq. 9 then amplifies the wrong directions by
+    1/|d(m)| ~ 90 and the first deflated cycle raises the residual.  The
+    solve must notice, return to the x before that cycle, finish without
+    deflation to the FP64 tolerance (judged by the oracle's D(m)) and say so."""
+    g = ovl.Geometry(c1["dims"])
+    gauge = gu.make_gauge(g, c1["U"], [(F32, 1)])
+    s = ovl.Sign(c1["lo"], c1["hi"], n=200)
+    rng = np.random.default_rng(5)
+    nvec = 8
+    N = c1["lat"].N
+    A = rng.standard_normal((N * 12, nvec)) + 1j * rng.standard_normal((N * 12, nvec))
+    Qm, _ = np.linalg.qr(A)
+    Xi = np.ascontiguousarray(Qm.T).reshape(nvec, N, 4, 3)
+    d = 1e-3 * np.exp(1j * rng.uniform(0, 2 * np.pi, nvec))
+    V = gu.pack(g, Xi, F64, nvec)
+    defl = ovl.Deflation(g, V, d)
+    m, R = 0.01, 4
+    bs = si.point_sources(c1["dims"])[:R]
+    x = torch.zeros(g.spinor_bytes(F64, R), dtype=torch.uint8, device=gu.DEV)
+    opts = ovl.SolveOpts(F32, 1e-3, 0, 1, 60)
+    opts.deflation = defl.handle.value
+    stt = ovl.SolveStats()
+    rc = ovl.ovl_cg_solve(x, gu.pack(g, bs, F64, R), R, gauge, RHO, m, s, None, 1e-10, 20000, opts,
+                          ctypes.byref(stt), None)
+    print("wrong pairs: rc %d, %d iterations, %d cycles, deflation dropped %d"
+          % (rc, stt.iterations, stt.restarts, stt.deflation_dropped))
+    assert rc == 0
+    assert stt.deflation_dropped == 1
+    so = sign.make_sign(c1["lo"], c1["hi"], 200)
+    xs = gu.unpack(g, x, F64, R)
     for r in range(R):
         res = bs[r] - sign.overlap_apply(c1["lat"], c1["U"], xs[r], RHO, m, so)
         assert np.linalg.norm(res) / np.linalg.norm(bs[r]) <= 1.05e-10
