@@ -98,6 +98,8 @@ def parse():
                     help="chiral-sector eigenvectors for a deflated 12-rhs CG at the main workload (0 = skip)")
     ap.add_argument("--deflate-eig", type=str, default="f32:1e-7:1e-5",
                     help="with --deflate: comma-separated prec:sign_delta:tol of the overlap eigensolver runs")
+    ap.add_argument("--deflate-mr", action="store_true",
+                    help="with --deflate: also solve with the minimal-residual form of the same deflation")
     ap.add_argument("--defl-ell", type=int, default=16,
                     help="16^3x32 block: chiral-sector eigenvectors for the deflated CG (eq. 9); 0 skips it")
     ap.add_argument("--shape", type=str, default="",
@@ -840,6 +842,22 @@ def main():
                 dc = dd[: 2 * nout.value].view(np.complex128)
                 defl = ovl.Deflation(g, Vd, dc)
                 r_defl = solve(prec, R, m0, args.graph_chunk, args.inner_tol, sgn_in, deflation=defl)
+                mr = None
+                if args.deflate_mr:
+                    # the minimal-residual form on the same pairs: Z = D(0) Xi
+                    # with the solve's FP64 operator, then the same solve
+                    Zd = torch.empty(g.spinor_bytes(ovl.OVL_F64, nout.value), dtype=torch.uint8, device=dev)
+                    torch.cuda.synchronize()
+                    tz = time.perf_counter()
+                    defl.prepare(gauge, rho, sgn, lm, Zd)
+                    torch.cuda.synchronize()
+                    tz = time.perf_counter() - tz
+                    r_mr = solve(prec, R, m0, args.graph_chunk, args.inner_tol, sgn_in, deflation=defl)
+                    mr = {"prepare_seconds": round(tz, 2), "cg": r_mr,
+                          "iteration_ratio": round(r_mr["iterations"] / max(1, base["iterations"]), 3),
+                          "eig_plus_prepare_plus_solve_vs_undeflated":
+                              round((est.seconds + tz + r_mr["seconds"]) / base["seconds"], 3)}
+                    del Zd
                 rec = {"sector_vectors": ellp, "eig_prec": pname, "eig_sign_n": sgn_eig.n, "eig_sign_delta": sdelta,
                        "eig_tol": stol, "pairs_of_D": nout.value, "eig_rc": erc, "eig_seconds": round(est.seconds, 1),
                        "eig_restart_cycles": est.iterations, "eig_dslash_applies": est.hw_applies,
@@ -847,7 +865,8 @@ def main():
                        "abs_d_max": float(np.abs(dc[-1])), "cg": r_defl,
                        "iteration_ratio": round(r_defl["iterations"] / max(1, base["iterations"]), 3),
                        "time_ratio": round(r_defl["seconds"] / base["seconds"], 3),
-                       "eig_plus_solve_vs_undeflated": round((est.seconds + r_defl["seconds"]) / base["seconds"], 3)}
+                       "eig_plus_solve_vs_undeflated": round((est.seconds + r_defl["seconds"]) / base["seconds"], 3),
+                       "minimal_residual": mr}
                 cg["deflated_%s_12rhs_m%.2f_eig_%s" % (args.prec, m0, pname)] = rec
                 log("CG deflated m=%.2f: %s" % (m0, rec))
                 del defl, Vd

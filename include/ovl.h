@@ -482,8 +482,23 @@ int ovl_host_heev(int n, const double* A, double* w, double* V);
 int ovl_overlap_eigs(const ovl_gauge* u, double rho, const ovl_sign* sign, const ovl_lowmodes* lowmodes, ovl_prec prec,
                      int sector, int ell, int K, void* V, double* d, int* nout, double tol, int max_iter,
                      ovl_eig_stats* stats, ovl_stream_t s);
+/* ovl_deflation_prepare: switches the deflation to its minimal-residual
+ *   form for approximate eigenpairs: Z = D(0) Xi (n FP64 spinors written to
+ *   the caller-owned device buffer Z, which the handle then BORROWS; D(0)
+ *   with rho, sign and lowmodes, which must be those of the solves that use
+ *   the handle) and the n x n Gram matrices of Z and Xi.  A cycle then adds
+ *   x += Xi y with y minimising ||r - D(m) Xi y|| (D(m) Xi = (1 - m/(2 rho)) Z
+ *   + m Xi, the small normal equations solved on the host), and hands the
+ *   inner solve r - D(m) Xi y, the exact new residual.  For exact
+ *   eigenpairs it is eq. 9; for approximate ones the correction can only
+ *   lower the residual.  Costs n FP64 sign applications (in batches of 12)
+ *   once.  OVL_E_ARG for a different lattice, rho <= 0; OVL_E_ALIAS for
+ *   Z == Xi; OVL_E_NAN for a non-finite Gram entry.
+ */
 int ovl_deflation_create(const ovl_geom* g, int n, const void* Xi, const double* d, ovl_deflation** out);
 int ovl_deflation_destroy(ovl_deflation* df);
+int ovl_deflation_prepare(ovl_deflation* df, const ovl_gauge* u, double rho, const ovl_sign* sign,
+                          const ovl_lowmodes* lowmodes, void* Z, ovl_stream_t s);
 
 /* --------------------------------------------------- learned preconditioner
  * A 2-layer gauge-equivariant parallel-transport convolution network

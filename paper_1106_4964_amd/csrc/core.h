@@ -570,6 +570,12 @@ struct ovl_deflation {
   int n;
   const void* Xi;                       // borrowed: n FP64 spinors
   std::vector<std::complex<double>> d;  // eigenvalues of D
+  // minimal-residual form (after ovl_deflation_prepare): Z = D(0) Xi
+  // (borrowed, n FP64 spinors) for the rho it was made with, and the Gram
+  // matrices ZZ = Z^dag Z, ZX = Z^dag Xi, XX = Xi^dag Xi (column-major n x n)
+  const void* Z = nullptr;
+  double rho = 0.0;
+  std::vector<std::complex<double>> ZZ, ZX, XX;
 };
 
 struct ovl_net {

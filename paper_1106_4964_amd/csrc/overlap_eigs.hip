@@ -311,18 +311,139 @@ int ovl_deflation_destroy(ovl_deflation* df) {
   return OVL_OK;
 }
 
+int ovl_deflation_prepare(ovl_deflation* df, const ovl_gauge* u, double rho, const ovl_sign* sgn,
+                          const ovl_lowmodes* lm, void* Z, ovl_stream_t st) {
+  return guard([&] {
+    OVL_REQUIRE(df && u && sgn && Z, OVL_E_ARG, "null argument");
+    OVL_REQUIRE(df->geom.N == u->geom.N, OVL_E_ARG, "deflation and gauge field have different lattices");
+    OVL_REQUIRE(rho > 0.0 && std::isfinite(rho), OVL_E_ARG, "need rho > 0");
+    OVL_REQUIRE(Z != df->Xi, OVL_E_ALIAS, "Z must not be the eigenvector buffer");
+    if (lm && lm->ell == 0) lm = nullptr;
+    if (lm) OVL_REQUIRE(lm->geom.N == u->geom.N, OVL_E_ARG, "low modes and gauge field have different lattices");
+    hipStream_t s = static_cast<hipStream_t>(st);
+    const ovl_geom* g = &df->geom;
+    const int n = df->n;
+    const size_t v64 = spinor_vec_bytes(g, OVL_F64);
+    auto at = [&](const void* base, int i) { return static_cast<const char*>(base) + static_cast<size_t>(i) * v64; };
+    // Z = D(0) Xi = rho D Xi, in batches of up to 12 vectors
+    for (int i0 = 0; i0 < n; i0 += OVL_MAX_RHS) {
+      const int nb = std::min(OVL_MAX_RHS, n - i0);
+      overlap_apply(static_cast<char*>(Z) + static_cast<size_t>(i0) * v64, at(df->Xi, i0), u, rho, 0.0, sgn, lm,
+                    1 /* D(m) */, OVL_F64, nb, s);
+    }
+    // Gram matrices, column by column in batches of up to 12
+    WsBuf cb(sizeof(double2) * static_cast<size_t>(n) * OVL_MAX_RHS, s);
+    std::vector<double2> h(static_cast<size_t>(n) * OVL_MAX_RHS);
+    std::vector<zc> ZZ(static_cast<size_t>(n) * n), ZX(ZZ.size()), XX(ZZ.size());
+    auto gram = [&](const void* A, const void* B, std::vector<zc>& out) {  // out[i + n j] = A_i^dag B_j
+      for (int j0 = 0; j0 < n; j0 += OVL_MAX_RHS) {
+        const int nb = std::min(OVL_MAX_RHS, n - j0);
+        block_dot(g, A, n, at(B, j0), OVL_F64, nb, static_cast<double2*>(cb.p), s);
+        OVL_HIP(hipMemcpyAsync(h.data(), cb.p, sizeof(double2) * static_cast<size_t>(n) * nb, hipMemcpyDeviceToHost, s));
+        OVL_HIP(hipStreamSynchronize(s));
+        for (int i = 0; i < n; ++i)
+          for (int r = 0; r < nb; ++r) {
+            const double2 c = h[static_cast<size_t>(i) * nb + r];
+            OVL_REQUIRE(std::isfinite(c.x) && std::isfinite(c.y), OVL_E_NAN, "non-finite Gram matrix entry");
+            out[i + static_cast<size_t>(n) * (j0 + r)] = zc(c.x, c.y);
+          }
+      }
+    };
+    gram(Z, Z, ZZ);
+    gram(Z, df->Xi, ZX);
+    gram(df->Xi, df->Xi, XX);
+    df->Z = Z;
+    df->rho = rho;
+    df->ZZ.swap(ZZ);
+    df->ZX.swap(ZX);
+    df->XX.swap(XX);
+    return OVL_OK;
+  });
+}
+
 }  // extern "C"
 
 namespace ovl {
 
+namespace {
+
+// Solves the n x n complex system A Y = B for R right-hand sides in place
+// (Gaussian elimination with partial pivoting; A column-major, B[i*R + r]).
+void host_solve(std::vector<zc>& A, std::vector<zc>& B, int n, int R) {
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int i = c + 1; i < n; ++i)
+      if (std::abs(A[i + static_cast<size_t>(n) * c]) > std::abs(A[piv + static_cast<size_t>(n) * c])) piv = i;
+    OVL_REQUIRE(std::abs(A[piv + static_cast<size_t>(n) * c]) > 0.0, OVL_E_BREAKDOWN,
+                "deflation: singular projected system (linearly dependent eigenvectors)");
+    if (piv != c) {
+      for (int k = 0; k < n; ++k) std::swap(A[c + static_cast<size_t>(n) * k], A[piv + static_cast<size_t>(n) * k]);
+      for (int r = 0; r < R; ++r) std::swap(B[static_cast<size_t>(c) * R + r], B[static_cast<size_t>(piv) * R + r]);
+    }
+    const zc dgn = A[c + static_cast<size_t>(n) * c];
+    for (int i = c + 1; i < n; ++i) {
+      const zc f = A[i + static_cast<size_t>(n) * c] / dgn;
+      if (f == zc(0.0, 0.0)) continue;
+      for (int k = c; k < n; ++k) A[i + static_cast<size_t>(n) * k] -= f * A[c + static_cast<size_t>(n) * k];
+      for (int r = 0; r < R; ++r) B[static_cast<size_t>(i) * R + r] -= f * B[static_cast<size_t>(c) * R + r];
+    }
+  }
+  for (int i = n - 1; i >= 0; --i)
+    for (int r = 0; r < R; ++r) {
+      zc v = B[static_cast<size_t>(i) * R + r];
+      for (int k = i + 1; k < n; ++k) v -= A[i + static_cast<size_t>(n) * k] * B[static_cast<size_t>(k) * R + r];
+      B[static_cast<size_t>(i) * R + r] = v / A[i + static_cast<size_t>(n) * i];
+    }
+}
+
+}  // namespace
+
 // The low part of eq. 9 for a batch of FP64 residuals r (R vectors):
 // x += sum_i xi_i (xi_i^dag r) / (rho d_i + m (1 - d_i / 2)),
 // r -= sum_i xi_i (xi_i^dag r).
+// After ovl_deflation_prepare, the minimal-residual form instead: with
+// W = D(m) Xi = a Z + m Xi (a = 1 - m / (2 rho), Z = D(0) Xi), the y that
+// minimises ||r - W y|| solves (W^dag W) y = W^dag r; then x += Xi y and
+// r -= W y, which is r's exact update.  For exact eigenpairs (orthonormal,
+// W = Xi diag(d(m))) both forms give the same y.
 void deflate(const ovl_deflation* df, double rho, double m, void* x, void* r, int R, hipStream_t s) {
   const ovl_geom* g = &df->geom;
   const int n = df->n;
   WsBuf cbuf(sizeof(double2) * static_cast<size_t>(n) * R, s);
   double2* C = static_cast<double2*>(cbuf.p);
+  if (df->Z) {
+    const double a = 1.0 - m / (2.0 * rho);
+    WsBuf cbuf2(sizeof(double2) * static_cast<size_t>(n) * R, s);
+    block_dot(g, df->Xi, n, r, OVL_F64, R, C, s);
+    block_dot(g, df->Z, n, r, OVL_F64, R, static_cast<double2*>(cbuf2.p), s);
+    std::vector<double2> h1(static_cast<size_t>(n) * R), h2(h1.size());
+    OVL_HIP(hipMemcpyAsync(h1.data(), C, sizeof(double2) * h1.size(), hipMemcpyDeviceToHost, s));
+    OVL_HIP(hipMemcpyAsync(h2.data(), cbuf2.p, sizeof(double2) * h2.size(), hipMemcpyDeviceToHost, s));
+    OVL_HIP(hipStreamSynchronize(s));
+    std::vector<zc> G(static_cast<size_t>(n) * n), Y(h1.size());
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < n; ++i) {
+        const size_t ij = i + static_cast<size_t>(n) * j, ji = j + static_cast<size_t>(n) * i;
+        G[ij] = a * a * df->ZZ[ij] + a * m * (df->ZX[ij] + std::conj(df->ZX[ji])) + m * m * df->XX[ij];
+      }
+    for (size_t k = 0; k < Y.size(); ++k) Y[k] = a * zc(h2[k].x, h2[k].y) + m * zc(h1[k].x, h1[k].y);
+    host_solve(G, Y, n, R);
+    std::vector<double2> kx(Y.size()), kz(Y.size()), kr(Y.size());
+    for (size_t k = 0; k < Y.size(); ++k) {
+      kx[k] = make_double2(Y[k].real(), Y[k].imag());
+      kz[k] = make_double2(-a * Y[k].real(), -a * Y[k].imag());
+      kr[k] = make_double2(-m * Y[k].real(), -m * Y[k].imag());
+    }
+    WsBuf dx(sizeof(double2) * kx.size(), s), dz(sizeof(double2) * kz.size(), s), dr(sizeof(double2) * kr.size(), s);
+    OVL_HIP(hipMemcpyAsync(dx.p, kx.data(), sizeof(double2) * kx.size(), hipMemcpyHostToDevice, s));
+    OVL_HIP(hipMemcpyAsync(dz.p, kz.data(), sizeof(double2) * kz.size(), hipMemcpyHostToDevice, s));
+    OVL_HIP(hipMemcpyAsync(dr.p, kr.data(), sizeof(double2) * kr.size(), hipMemcpyHostToDevice, s));
+    block_axpy(g, df->Xi, n, static_cast<const double2*>(dx.p), x, OVL_F64, R, true, s);
+    block_axpy(g, df->Z, n, static_cast<const double2*>(dz.p), r, OVL_F64, R, true, s);
+    block_axpy(g, df->Xi, n, static_cast<const double2*>(dr.p), r, OVL_F64, R, true, s);
+    OVL_HIP(hipStreamSynchronize(s));  // the host coefficient arrays end with this scope
+    return;
+  }
   block_dot(g, df->Xi, n, r, OVL_F64, R, C, s);
   std::vector<double2> h(static_cast<size_t>(n) * R), hx(h.size());
   OVL_HIP(hipMemcpyAsync(h.data(), C, sizeof(double2) * h.size(), hipMemcpyDeviceToHost, s));

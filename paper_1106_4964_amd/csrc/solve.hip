@@ -160,8 +160,11 @@ int cg_solve(void* x, const void* b, int R, const ovl_gauge* u, double rho, doub
   OVL_REQUIRE(!chiral || !(opt.harvest_x && opt.harvest_b && opt.harvest_cap > 0), OVL_E_ARG,
               "chiral solves do not harvest training pairs");
   OVL_REQUIRE(!chiral || !opt.deflation, OVL_E_ARG, "chiral solves do not take a deflation");
-  if (opt.deflation)
+  if (opt.deflation) {
     OVL_REQUIRE(opt.deflation->geom.N == u->geom.N, OVL_E_ARG, "deflation and gauge field have different lattices");
+    OVL_REQUIRE(!opt.deflation->Z || opt.deflation->rho == rho, OVL_E_ARG,
+                "the deflation was prepared with another rho");
+  }
 
   Solver S{};
   S.u = u;

@@ -172,6 +172,7 @@ _SIGS = {
     "ovl_overlap_eigs": (P, D, P, P, I, I, I, I, P, P, P, D, I, P, ST),
     "ovl_deflation_create": (P, I, P, P, P),
     "ovl_deflation_destroy": (P,),
+    "ovl_deflation_prepare": (P, P, D, P, P, P, ST),
     "ovl_fgcr_solve": (P, P, I, P, D, D, P, P, P, I, D, I, P, P, ST),
     "ovl_net_create": (P, I, P),
     "ovl_net_destroy": (P,),
@@ -440,6 +441,12 @@ class Deflation:
         self.handle = h
         self.Xi = Xi_dev  # keep the borrowed buffer alive
         self.n = len(d)
+        self.Z = None
+
+    def prepare(self, gauge, rho, sign, lowmodes, Z_dev, stream=None):
+        """Minimal-residual form: Z = D(0) Xi into Z_dev (borrowed from then on)."""
+        ovl_deflation_prepare(self, gauge, rho, sign, lowmodes, Z_dev, stream)
+        self.Z = Z_dev
 
     def __del__(self, _lib=lib, _exiting=sys.is_finalizing):
         # at interpreter exit module globals may be gone and the process end

@@ -200,3 +200,83 @@ def test_wrong_eigenpairs_are_dropped(c1):
     for r in range(R):
         res = bs[r] - sign.overlap_apply(c1["lat"], c1["U"], xs[r], RHO, m, so)
         assert np.linalg.norm(res) / np.linalg.norm(bs[r]) <= 1.05e-10
+
+
+def _deflated_solve(c1, g, gauge, s, defl, rho=RHO, R=4, m=0.01):
+    b = gu.pack(g, si.point_sources(c1["dims"])[:R], F64, R)
+    x = torch.zeros(g.spinor_bytes(F64, R), dtype=torch.uint8, device=gu.DEV)
+    opts = ovl.SolveOpts(F32, 1e-3, 0, 1, 60)
+    opts.deflation = defl.handle.value if defl is not None else None
+    stt = ovl.SolveStats()
+    rc = ovl.ovl_cg_solve(x, b, R, gauge, rho, m, s, None, 1e-10, 20000, opts, ctypes.byref(stt), None)
+    return rc, stt, gu.unpack(g, x, F64, R)
+
+
+def _check_solution(c1, xs, m=0.01):
+    so = sign.make_sign(c1["lo"], c1["hi"], 200)
+    bs = si.point_sources(c1["dims"])[: len(xs)]
+    for r in range(len(xs)):
+        res = bs[r] - sign.overlap_apply(c1["lat"], c1["U"], xs[r], RHO, m, so)
+        assert np.linalg.norm(res) / np.linalg.norm(bs[r]) <= 1.05e-10
+
+
+def test_minimal_residual_deflation(c1):
+    """ovl_deflation_prepare: the correction in span(Xi) that minimises the
+    residual, with D(m) Xi from Z = D(0) Xi.  Accurate (FP64) pairs: the same
+    iterations as eq. 9.  FP32-sign pairs: no more than eq. 9 with the same
+    pairs.  Wrong pairs (random orthonormal vectors, |d| = 1e-3): the
+    correction cannot raise the residual, so nothing is dropped.  Every
+    solution meets 1e-10 through the oracle's D(m)."""
+    g = ovl.Geometry(c1["dims"])
+    gauge = gu.make_gauge(g, c1["U"], [(F32, 1)])
+    s = ovl.Sign(c1["lo"], c1["hi"], n=200)
+    ell = 10
+    v64 = g.spinor_bytes(F64)
+    res = {}
+    for name, prec, tol in (("fp64 pairs", F64, 1e-10), ("fp32 pairs", F32, 1e-5)):
+        rc, V, d, n, st = _gpu_eigs(c1, g, gauge, s, ell, 48, 1, tol=tol, prec=prec)
+        assert rc == 0
+        its = []
+        for prepared in (False, True):
+            defl = ovl.Deflation(g, V, d)
+            if prepared:
+                Z = torch.empty(n * v64, dtype=torch.uint8, device=gu.DEV)
+                defl.prepare(gauge, RHO, s, None, Z)
+            rc, stt, xs = _deflated_solve(c1, g, gauge, s, defl)
+            assert rc == 0 and stt.deflation_dropped == 0
+            _check_solution(c1, xs)
+            its.append(stt.iterations)
+        res[name] = its
+    rng = np.random.default_rng(5)
+    N = c1["lat"].N
+    A = rng.standard_normal((N * 12, 8)) + 1j * rng.standard_normal((N * 12, 8))
+    Xi = np.ascontiguousarray(np.linalg.qr(A)[0].T).reshape(8, N, 4, 3)
+    defl = ovl.Deflation(g, gu.pack(g, Xi, F64, 8), 1e-3 * np.exp(1j * rng.uniform(0, 2 * np.pi, 8)))
+    Z = torch.empty(8 * v64, dtype=torch.uint8, device=gu.DEV)
+    defl.prepare(gauge, RHO, s, None, Z)
+    rc, stt, xs = _deflated_solve(c1, g, gauge, s, defl)
+    print("iterations (eq. 9, minimal residual):", res, "; wrong pairs prepared: %d, dropped %d"
+          % (stt.iterations, stt.deflation_dropped))
+    assert rc == 0 and stt.deflation_dropped == 0
+    _check_solution(c1, xs)
+    assert abs(res["fp64 pairs"][1] - res["fp64 pairs"][0]) <= 2
+    assert res["fp32 pairs"][1] <= res["fp32 pairs"][0] + 1
+
+
+def test_prepare_argument_errors(c1):
+    g = ovl.Geometry(c1["dims"])
+    gauge = gu.make_gauge(g, c1["U"], [(F32, 1)])
+    s = ovl.Sign(c1["lo"], c1["hi"], n=50)
+    rng = np.random.default_rng(1)
+    N = c1["lat"].N
+    A = rng.standard_normal((N * 12, 2)) + 1j * rng.standard_normal((N * 12, 2))
+    V = gu.pack(g, np.ascontiguousarray(np.linalg.qr(A)[0].T).reshape(2, N, 4, 3), F64, 2)
+    defl = ovl.Deflation(g, V, np.array([0.5 + 0.1j, 0.5 - 0.1j]))
+    Z = torch.empty(2 * g.spinor_bytes(F64), dtype=torch.uint8, device=gu.DEV)
+    with pytest.raises(ovl.OvlError):
+        defl.prepare(gauge, 0.0, s, None, Z)  # rho <= 0
+    with pytest.raises(ovl.OvlError):
+        defl.prepare(gauge, RHO, s, None, V)  # Z aliasing Xi
+    defl.prepare(gauge, RHO, s, None, Z)
+    with pytest.raises(ovl.OvlError):
+        _deflated_solve(c1, g, gauge, s, defl, rho=1.4)  # prepared with another rho
