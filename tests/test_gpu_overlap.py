@@ -83,6 +83,37 @@ def test_projection_parity(nrhs):
         assert gu.max_rel_err(got_w[r], want_w) < 1e-13
 
 
+@pytest.mark.parametrize("nrhs", [1, 12])
+@pytest.mark.parametrize("prec", [ovl.OVL_F32, ovl.OVL_F16, ovl.OVL_BF16])
+def test_projection_parity_low_precision(prec, nrhs):
+    """Batches below FP64 are projected on the library's FP32 copy of the
+    basis (FP64 accumulation): psi_h and w against the oracle's FP64
+    projection of the same stored input, element by element, to the output
+    precision's rounding (plus the copy's ~1e-7)."""
+    dims = (6, 6, 6, 8)
+    g = ovl.Geometry(dims)
+    ell = 21
+    V = si.orthonormal_spinors(dims, ell, seed=7)
+    lam = np.linspace(-0.9, 0.8, ell)
+    lm = ovl.LowModes(g, _lowmodes_dev(g, V), lam)
+    psi = np.stack([si.gaussian_spinor(dims, 30 + r) for r in range(nrhs)])
+    inp = gu.pack(g, psi, prec, nrhs)
+    psi_stored = gu.unpack(g, inp, prec, nrhs).reshape(nrhs, g.N, 4, 3)
+    ph = gu.empty_field(g, prec, nrhs)
+    w = gu.empty_field(g, prec, nrhs)
+    ovl.ovl_lowmodes_project(lm, inp, ph, w, prec, nrhs, None)
+    got_h = gu.unpack(g, ph, prec, nrhs).reshape(nrhs, g.N, 4, 3)
+    got_w = gu.unpack(g, w, prec, nrhs).reshape(nrhs, g.N, 4, 3)
+    bound = 4 * gu.UNIT_ROUNDOFF[prec] + 5e-7
+    worst = 0.0
+    for r in range(nrhs):
+        c, want_h = sign.project_low(V, psi_stored[r])
+        want_w = ((np.sign(lam) * c) @ V.reshape(ell, -1)).reshape(g.N, 4, 3)
+        worst = max(worst, gu.max_rel_err(got_h[r], want_h), gu.max_rel_err(got_w[r], want_w))
+    print("projection, precision %d, %d rhs: max rel err %.2e (bound %.2e)" % (prec, nrhs, worst, bound))
+    assert worst < bound
+
+
 @pytest.mark.parametrize("dagger", [0, 1])
 def test_overlap_with_lowmodes_f64_ragged(dagger):
     """6x6x6x8 (ragged tiles), synthetic orthonormal 'low modes', 12 RHS."""
