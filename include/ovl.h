@@ -190,15 +190,10 @@ int ovl_sign_coeffs(const ovl_sign* s, double* c, int cap);
  * ovl_lowmodes_create: V is a caller-owned device buffer of ell FP64 spinors
  *   (library layout, back to back), orthonormal; lambda is a host array of
  *   ell eigenvalues of H_w (copied).  The handle BORROWS V: it must stay
- *   valid and unchanged for the handle's lifetime.  It also keeps an FP32
- *   copy of V (ell * N * 96 bytes, half the size of V, made once here, the
- *   device synchronised before and after), which the projections of FP32,
- *   F16 and BF16 batches read instead of V; OVL_E_NOMEM if it does not fit.
+ *   valid and unchanged for the handle's lifetime.
  * ovl_lowmodes_project: psi_h = in - sum_i (eta_i^dag in) eta_i and
  *   w = sum_i sign(lambda_i) (eta_i^dag in) eta_i for a batch of nrhs <= 12
- *   spinors at precision prec; the inner products accumulate in FP64 (on
- *   the FP32 copy of the basis below FP64 precision, which adds ~1e-7
- *   relative error, below those precisions' own rounding).
+ *   spinors at precision prec; the inner products accumulate in FP64.
  */
 int ovl_lowmodes_create(const ovl_geom* g, int ell, const void* V, const double* lambda, ovl_lowmodes** out);
 int ovl_lowmodes_destroy(ovl_lowmodes* lm);

@@ -39,37 +39,11 @@ __device__ inline Cx<double> load_cx(const char* base, int row, int h, int Nh) {
 }
 
 // Basis elements are read once per sweep: non-temporal, so the batch's
-// blocks (reused across the 24 rows of a site tile) stay in L2.  VP = OVL_F64:
-// the FP64 basis, 16 bytes per element; OVL_F32: its compact copy, 8 bytes
-// per element in the same (row, h) order, so a wave still reads one
-// contiguous run per row.
-template <int VP>
+// blocks (reused across the 24 rows of a site tile) stay in L2.
 __device__ inline Cx<double> load_basis(const char* base, int row, int h, int Nh) {
-  if constexpr (VP == OVL_F64) {
-    typedef double f64x2_t __attribute__((ext_vector_type(2)));
-    const f64x2_t v =
-        __builtin_nontemporal_load(reinterpret_cast<const f64x2_t*>(base + cx_offset<OVL_F64>(row, h, Nh)));
-    return {v.x, v.y};
-  } else {
-    typedef float f32x2_t __attribute__((ext_vector_type(2)));
-    const f32x2_t v = __builtin_nontemporal_load(
-        reinterpret_cast<const f32x2_t*>(base + (static_cast<size_t>(row) * Nh + h) * 8));
-    return {static_cast<double>(v.x), static_cast<double>(v.y)};
-  }
-}
-
-// Bytes per basis vector at basis precision VP.
-template <int VP>
-inline size_t basis_vec_bytes(const ovl_geom* g) {
-  return VP == OVL_F64 ? spinor_vec_bytes(g, OVL_F64) : static_cast<size_t>(24) * g->geo.Nh * 8;
-}
-
-__global__ void basis_to_f32_kernel(const double2* __restrict__ src, float2* __restrict__ dst, size_t n) {
-  for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < n;
-       i += static_cast<size_t>(gridDim.x) * blockDim.x) {
-    const double2 v = src[i];
-    dst[i] = make_float2(static_cast<float>(v.x), static_cast<float>(v.y));
-  }
+  typedef double f64x2_t __attribute__((ext_vector_type(2)));
+  const f64x2_t v = __builtin_nontemporal_load(reinterpret_cast<const f64x2_t*>(base + cx_offset<OVL_F64>(row, h, Nh)));
+  return {v.x, v.y};
 }
 
 template <int P>
@@ -95,7 +69,7 @@ __device__ inline double wsum(double v) {
 // batch is staged in LDS (as FP64) once per block.
 // EX: the batch has exactly RMAX vectors (R is a compile-time constant, so
 // per-rhs guards and coefficient strides fold away).
-template <int PP, int RMAX, int IW, bool EX, int VP>
+template <int PP, int RMAX, int IW, bool EX>
 __global__ __launch_bounds__(PJ_WAVES * 64) void dot_kernel(int Nh, int ell, const char* V, size_t vstrideV,
                                                              const char* psi, size_t vstrideP, int R,
                                                              double2* partial) {
@@ -123,7 +97,7 @@ __global__ __launch_bounds__(PJ_WAVES * 64) void dot_kernel(int Nh, int ell, con
     Cx<double> v[IW];
 #pragma unroll
     for (int j = 0; j < IW; ++j)
-      v[j] = (ibase + j < ell && h < Nh) ? load_basis<VP>(V + (ibase + j) * vstrideV, row, h, Nh)
+      v[j] = (ibase + j < ell && h < Nh) ? load_basis(V + (ibase + j) * vstrideV, row, h, Nh)
                                          : Cx<double>{0.0, 0.0};
     __syncthreads();
     for (int k = threadIdx.x; k < R * PJ_TILE; k += blockDim.x) {
@@ -184,7 +158,7 @@ __global__ __launch_bounds__(256) void axpy_kernel(int Nh, int ell, const char* 
   for (int r = 0; r < RMAX; ++r)
     y[r] = (KEEP && r < R) ? load_cx<PP>(Y + r * vstrideP, row, h, Nh) : Cx<double>{0.0, 0.0};
   for (int i = 0; i < ell; ++i) {
-    const Cx<double> v = load_basis<OVL_F64>(V + i * vstrideV, row, h, Nh);
+    const Cx<double> v = load_basis(V + i * vstrideV, row, h, Nh);
 #pragma unroll
     for (int r = 0; r < RMAX; ++r) {
       if (r < R) {
@@ -202,7 +176,7 @@ __global__ __launch_bounds__(256) void axpy_kernel(int Nh, int ell, const char* 
 }
 
 // psi_h = psi - sum_i C_i eta_i, w = [gamma5] sum_i sign_i C_i eta_i.
-template <int PP, int RMAX, bool EX, int VP>
+template <int PP, int RMAX, bool EX>
 __global__ __launch_bounds__(256) void project_kernel(int Nh, int ell, const char* V, size_t vstrideV,
                                                       const char* psi, char* psih, char* w, size_t vstrideP, int R,
                                                       const double2* __restrict__ coef,
@@ -219,7 +193,7 @@ __global__ __launch_bounds__(256) void project_kernel(int Nh, int ell, const cha
     ww[r] = {0.0, 0.0};
   }
   for (int i = 0; i < ell; ++i) {
-    const Cx<double> v = load_basis<VP>(V + i * vstrideV, row, h, Nh);
+    const Cx<double> v = load_basis(V + i * vstrideV, row, h, Nh);
     const double s = sgn[i];
 #pragma unroll
     for (int r = 0; r < RMAX; ++r) {
@@ -269,13 +243,13 @@ __global__ __launch_bounds__(256) void rotate_kernel(int Nh, int K, int k, char*
   }
 }
 
-template <int PP, int RMAX, int IW, bool EX = false, int VP = OVL_F64>
+template <int PP, int RMAX, int IW, bool EX = false>
 void dot_go(const ovl_geom* g, const void* V, int ell, const void* psi, int R, double2* C, double2* part, int G,
             hipStream_t s) {
   const int Nh = g->geo.Nh;
-  const size_t vsV = basis_vec_bytes<VP>(g), vsP = spinor_vec_bytes(g, PP);
+  const size_t vsV = spinor_vec_bytes(g, OVL_F64), vsP = spinor_vec_bytes(g, PP);
   const int groups = (ell + PJ_WAVES * IW - 1) / (PJ_WAVES * IW);
-  hipLaunchKernelGGL((dot_kernel<PP, RMAX, IW, EX, VP>), dim3(groups, G), dim3(PJ_WAVES * 64), 0, s, Nh, ell,
+  hipLaunchKernelGGL((dot_kernel<PP, RMAX, IW, EX>), dim3(groups, G), dim3(PJ_WAVES * 64), 0, s, Nh, ell,
                      static_cast<const char*>(V), vsV, static_cast<const char*>(psi), vsP, R, part);
   OVL_HIP(hipGetLastError());
   hipLaunchKernelGGL(dot_reduce_kernel, dim3((ell * R + 255) / 256), dim3(256), 0, s, ell, R, G,
@@ -284,33 +258,22 @@ void dot_go(const ovl_geom* g, const void* V, int ell, const void* psi, int R, d
 }
 
 // C = V^dag psi with the per-block partials in `part` (ell * G * R entries).
-template <int PP, int VP = OVL_F64>
+template <int PP>
 void dot_r(const ovl_geom* g, const void* V, int ell, const void* psi, int R, double2* C, double2* part, int G,
            hipStream_t s) {
-  if (R == 1) dot_go<PP, 1, 8, true, VP>(g, V, ell, psi, R, C, part, G, s);
-  else if (R <= 4) dot_go<PP, 4, 4, false, VP>(g, V, ell, psi, R, C, part, G, s);
-  else if (R == 12) dot_go<PP, 12, 2, true, VP>(g, V, ell, psi, R, C, part, G, s);
-  else dot_go<PP, 12, 2, false, VP>(g, V, ell, psi, R, C, part, G, s);
+  if (R == 1) dot_go<PP, 1, 8, true>(g, V, ell, psi, R, C, part, G, s);
+  else if (R <= 4) dot_go<PP, 4, 4>(g, V, ell, psi, R, C, part, G, s);
+  else if (R == 12) dot_go<PP, 12, 2, true>(g, V, ell, psi, R, C, part, G, s);
+  else dot_go<PP, 12, 2>(g, V, ell, psi, R, C, part, G, s);
 }
 
-// C = V^dag psi for an FP64 basis V, or (compact = true, prec below FP64)
-// for the compact FP32 copy of one.
 void dot_prec(const ovl_geom* g, const void* V, int ell, const void* psi, int prec, int R, double2* C, double2* part,
-              int G, hipStream_t s, bool compact = false) {
+              int G, hipStream_t s) {
   switch (prec) {
     case OVL_F64: dot_r<OVL_F64>(g, V, ell, psi, R, C, part, G, s); break;
-    case OVL_F32:
-      if (compact) dot_r<OVL_F32, OVL_F32>(g, V, ell, psi, R, C, part, G, s);
-      else dot_r<OVL_F32>(g, V, ell, psi, R, C, part, G, s);
-      break;
-    case OVL_F16:
-      if (compact) dot_r<OVL_F16, OVL_F32>(g, V, ell, psi, R, C, part, G, s);
-      else dot_r<OVL_F16>(g, V, ell, psi, R, C, part, G, s);
-      break;
-    case OVL_BF16:
-      if (compact) dot_r<OVL_BF16, OVL_F32>(g, V, ell, psi, R, C, part, G, s);
-      else dot_r<OVL_BF16>(g, V, ell, psi, R, C, part, G, s);
-      break;
+    case OVL_F32: dot_r<OVL_F32>(g, V, ell, psi, R, C, part, G, s); break;
+    case OVL_F16: dot_r<OVL_F16>(g, V, ell, psi, R, C, part, G, s); break;
+    case OVL_BF16: dot_r<OVL_BF16>(g, V, ell, psi, R, C, part, G, s); break;
     default: throw Error(OVL_E_PRECISION, "unknown precision");
   }
 }
@@ -337,26 +300,25 @@ void axpy_r(const ovl_geom* g, const void* V, int ell, const double2* K, void* Y
   else axpy_go<PP, 12>(g, V, ell, K, Y, R, keep, s);
 }
 
-template <int PP, int RMAX, bool EX, int VP>
+template <int PP, int RMAX, bool EX = false>
 void project_go(const ovl_lowmodes* lm, const void* psi, void* psih, void* w, int R, int g5w, const double2* C,
                 hipStream_t s) {
   const ovl_geom* g = &lm->geom;
   const int Nh = g->geo.Nh;
-  const size_t vsV = basis_vec_bytes<VP>(g), vsP = spinor_vec_bytes(g, PP);
-  const void* V = VP == OVL_F64 ? lm->V : lm->V32;
-  hipLaunchKernelGGL((project_kernel<PP, RMAX, EX, VP>), dim3(((Nh + 255) / 256) * 24), dim3(256), 0, s, Nh, lm->ell,
-                     static_cast<const char*>(V), vsV, static_cast<const char*>(psi), static_cast<char*>(psih),
+  const size_t vsV = spinor_vec_bytes(g, OVL_F64), vsP = spinor_vec_bytes(g, PP);
+  hipLaunchKernelGGL((project_kernel<PP, RMAX, EX>), dim3(((Nh + 255) / 256) * 24), dim3(256), 0, s, Nh, lm->ell,
+                     static_cast<const char*>(lm->V), vsV, static_cast<const char*>(psi), static_cast<char*>(psih),
                      static_cast<char*>(w), vsP, R, C, lm->dev_sign, g5w);
   OVL_HIP(hipGetLastError());
 }
 
-template <int PP, int VP = OVL_F64>
+template <int PP>
 void project_r(const ovl_lowmodes* lm, const void* psi, void* psih, void* w, int R, int g5w, const double2* C,
                hipStream_t s) {
-  if (R == 1) project_go<PP, 1, true, VP>(lm, psi, psih, w, R, g5w, C, s);
-  else if (R <= 4) project_go<PP, 4, false, VP>(lm, psi, psih, w, R, g5w, C, s);
-  else if (R == 12) project_go<PP, 12, true, VP>(lm, psi, psih, w, R, g5w, C, s);
-  else project_go<PP, 12, false, VP>(lm, psi, psih, w, R, g5w, C, s);
+  if (R == 1) project_go<PP, 1, true>(lm, psi, psih, w, R, g5w, C, s);
+  else if (R <= 4) project_go<PP, 4>(lm, psi, psih, w, R, g5w, C, s);
+  else if (R == 12) project_go<PP, 12, true>(lm, psi, psih, w, R, g5w, C, s);
+  else project_go<PP, 12>(lm, psi, psih, w, R, g5w, C, s);
 }
 
 }  // namespace
@@ -391,14 +353,6 @@ void block_rotate_inplace(const ovl_geom* g, void* V, int K, const double2* S, i
   OVL_HIP(hipGetLastError());
 }
 
-void basis_to_f32(const ovl_geom* g, const void* V, int ell, void* V32, hipStream_t s) {
-  const size_t n = static_cast<size_t>(ell) * 24 * g->geo.Nh;
-  const int blocks = static_cast<int>(std::min<size_t>((n + 255) / 256, 8192));
-  hipLaunchKernelGGL(basis_to_f32_kernel, dim3(blocks), dim3(256), 0, s, static_cast<const double2*>(V),
-                     static_cast<float2*>(V32), n);
-  OVL_HIP(hipGetLastError());
-}
-
 namespace {
 // The projection with caller-provided scratch: C (ell * nrhs coefficients)
 // and the split-K partials of pass 1 (ell * G * nrhs).
@@ -406,24 +360,12 @@ void lowmode_project_ws(const ovl_lowmodes* lm, const void* psi, void* psih, voi
                         double2* C, double2* part, int G, hipStream_t s) {
   OVL_REQUIRE(nrhs >= 1 && nrhs <= OVL_MAX_RHS && lm->ell >= 1, OVL_E_ARG,
               "projection: 1 <= nrhs <= 12 and at least one low mode");
-  // batches below FP64 are projected on the compact FP32 copy of the basis
-  // (both passes, so psi_h stays orthogonal to the basis they use)
-  const bool compact = prec != OVL_F64 && lm->V32 != nullptr;
-  dot_prec(&lm->geom, compact ? lm->V32 : lm->V, lm->ell, psi, prec, nrhs, C, part, G, s, compact);
+  dot_prec(&lm->geom, lm->V, lm->ell, psi, prec, nrhs, C, part, G, s);
   switch (prec) {
     case OVL_F64: project_r<OVL_F64>(lm, psi, psih, w, nrhs, g5w, C, s); break;
-    case OVL_F32:
-      if (compact) project_r<OVL_F32, OVL_F32>(lm, psi, psih, w, nrhs, g5w, C, s);
-      else project_r<OVL_F32>(lm, psi, psih, w, nrhs, g5w, C, s);
-      break;
-    case OVL_F16:
-      if (compact) project_r<OVL_F16, OVL_F32>(lm, psi, psih, w, nrhs, g5w, C, s);
-      else project_r<OVL_F16>(lm, psi, psih, w, nrhs, g5w, C, s);
-      break;
-    case OVL_BF16:
-      if (compact) project_r<OVL_BF16, OVL_F32>(lm, psi, psih, w, nrhs, g5w, C, s);
-      else project_r<OVL_BF16>(lm, psi, psih, w, nrhs, g5w, C, s);
-      break;
+    case OVL_F32: project_r<OVL_F32>(lm, psi, psih, w, nrhs, g5w, C, s); break;
+    case OVL_F16: project_r<OVL_F16>(lm, psi, psih, w, nrhs, g5w, C, s); break;
+    case OVL_BF16: project_r<OVL_BF16>(lm, psi, psih, w, nrhs, g5w, C, s); break;
     default: throw Error(OVL_E_PRECISION, "unknown precision");
   }
 }

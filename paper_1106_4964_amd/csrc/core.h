@@ -562,11 +562,6 @@ struct ovl_lowmodes {
   const void* V;  // borrowed: ell FP64 spinors
   std::vector<double> lambda;
   double* dev_sign = nullptr;  // sign(lambda_i) on the device
-  // owned FP32 copy of V for the projections of FP32/F16/BF16 batches:
-  // [ell][24 rows][N/2] complex of 8 bytes (row = parity * 12 + component,
-  // the FP64 basis's element order at half the width)
-  void* V32 = nullptr;
-  size_t V32_bytes = 0;
 };
 
 // Eigenpairs of the massless overlap operator used to deflate D(m) (eq. 9).

@@ -77,9 +77,6 @@ void blas_norm2(int prec, size_t n16, const void* x, int nrhs, size_t vstride, d
 // index i*R + r.
 void block_dot(const ovl_geom* g, const void* V, int ell, const void* psi, int prec, int R, double2* C,
                hipStream_t s);
-// The FP32 copy of an FP64 basis of ell vectors (the low-mode basis's
-// compact form): element (vector i, row, h) becomes 8 bytes in the same order.
-void basis_to_f32(const ovl_geom* g, const void* V, int ell, void* V32, hipStream_t s);
 void block_axpy(const ovl_geom* g, const void* V, int ell, const double2* K, void* Y, int prec, int R, bool keep,
                 hipStream_t s);
 // In place: V[:, j] = sum_{i<K} V[:, i] S[i + K*j] for j < k (FP64 basis, S on the device, K <= 512).

@@ -543,20 +543,6 @@ int ovl_lowmodes_create(const ovl_geom* g, int ell, const void* V, const double*
       throw Error(OVL_E_NOMEM, "lowmodes: device allocation failed");
     }
     OVL_HIP(hipMemcpy(lm->dev_sign, sg.data(), sg.size() * sizeof(double), hipMemcpyHostToDevice));
-    if (ell > 0) {
-      // the compact FP32 copy that projections of lower-precision batches read
-      lm->V32_bytes = static_cast<size_t>(ell) * 24 * g->geo.Nh * 8;
-      if (hipMalloc(&lm->V32, lm->V32_bytes) != hipSuccess) {
-        (void)hipGetLastError();
-        (void)hipFree(lm->dev_sign);
-        delete lm;
-        throw Error(OVL_E_NOMEM, "lowmodes: device allocation of the FP32 basis copy failed");
-      }
-      mem_track(static_cast<int64_t>(lm->V32_bytes));
-      OVL_HIP(hipDeviceSynchronize());  // V as the caller left it
-      basis_to_f32(g, V, ell, lm->V32, nullptr);
-      OVL_HIP(hipDeviceSynchronize());
-    }
     *out = lm;
     return OVL_OK;
   });
@@ -565,10 +551,6 @@ int ovl_lowmodes_create(const ovl_geom* g, int ell, const void* V, const double*
 int ovl_lowmodes_destroy(ovl_lowmodes* lm) {
   if (lm) {
     if (lm->dev_sign) (void)hipFree(lm->dev_sign);
-    if (lm->V32) {
-      (void)hipFree(lm->V32);
-      mem_track(-static_cast<int64_t>(lm->V32_bytes));
-    }
     delete lm;
   }
   return OVL_OK;

@@ -86,10 +86,9 @@ def test_projection_parity(nrhs):
 @pytest.mark.parametrize("nrhs", [1, 12])
 @pytest.mark.parametrize("prec", [ovl.OVL_F32, ovl.OVL_F16, ovl.OVL_BF16])
 def test_projection_parity_low_precision(prec, nrhs):
-    """Batches below FP64 are projected on the library's FP32 copy of the
-    basis (FP64 accumulation): psi_h and w against the oracle's FP64
-    projection of the same stored input, element by element, to the output
-    precision's rounding (plus the copy's ~1e-7)."""
+    """Batches below FP64 (FP64 basis, FP64 accumulation): psi_h and w
+    against the oracle's FP64 projection of the same stored input, element
+    by element, to the output precision's rounding."""
     dims = (6, 6, 6, 8)
     g = ovl.Geometry(dims)
     ell = 21
@@ -104,7 +103,7 @@ def test_projection_parity_low_precision(prec, nrhs):
     ovl.ovl_lowmodes_project(lm, inp, ph, w, prec, nrhs, None)
     got_h = gu.unpack(g, ph, prec, nrhs).reshape(nrhs, g.N, 4, 3)
     got_w = gu.unpack(g, w, prec, nrhs).reshape(nrhs, g.N, 4, 3)
-    bound = 4 * gu.UNIT_ROUNDOFF[prec] + 5e-7
+    bound = 4 * gu.UNIT_ROUNDOFF[prec] + 1e-12
     worst = 0.0
     for r in range(nrhs):
         c, want_h = sign.project_low(V, psi_stored[r])
