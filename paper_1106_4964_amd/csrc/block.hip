@@ -192,18 +192,30 @@ __global__ __launch_bounds__(256) void project_kernel(int Nh, int ell, const cha
     ph[r] = (r < R) ? load_cx<PP>(psi + r * vstrideP, row, h, Nh) : Cx<double>{0.0, 0.0};
     ww[r] = {0.0, 0.0};
   }
-  for (int i = 0; i < ell; ++i) {
-    const Cx<double> v = load_basis(V + i * vstrideV, row, h, Nh);
-    const double s = sgn[i];
+  // the basis elements of the next PF modes are in flight while one is used
+  constexpr int PF = 4;
+  Cx<double> vb[PF];
 #pragma unroll
-    for (int r = 0; r < RMAX; ++r) {
-      if (r < R) {
-        const double2 cc = coef[i * R + r];
-        const double vr = v.re * cc.x - v.im * cc.y, vi = v.re * cc.y + v.im * cc.x;
-        ph[r].re -= vr;
-        ph[r].im -= vi;
-        ww[r].re = fma(s, vr, ww[r].re);
-        ww[r].im = fma(s, vi, ww[r].im);
+  for (int k = 0; k < PF; ++k) vb[k] = (k < ell) ? load_basis(V + k * vstrideV, row, h, Nh) : Cx<double>{0.0, 0.0};
+  for (int i0 = 0; i0 < ell; i0 += PF) {
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+      const int i = i0 + k;
+      if (i < ell) {
+        const Cx<double> v = vb[k];
+        if (i + PF < ell) vb[k] = load_basis(V + (i + PF) * vstrideV, row, h, Nh);
+        const double s = sgn[i];
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r) {
+          if (r < R) {
+            const double2 cc = coef[i * R + r];
+            const double vr = v.re * cc.x - v.im * cc.y, vi = v.re * cc.y + v.im * cc.x;
+            ph[r].re -= vr;
+            ph[r].im -= vi;
+            ww[r].re = fma(s, vr, ww[r].re);
+            ww[r].im = fma(s, vi, ww[r].im);
+          }
+        }
       }
     }
   }
