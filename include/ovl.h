@@ -170,13 +170,15 @@ int ovl_convert(const ovl_geom* g, const void* src, ovl_prec src_prec, void* dst
  * the relative error and held as Chebyshev coefficients c_0..c_n in
  * y = (2x - 1 - eps)/(1 - eps).  Where the Chebyshev interpolant of
  * x^{-1/2} at the n+1 Chebyshev-Gauss nodes already has delta <= 1e-12
- * (FP64 rounding), or n > 1000, that interpolant is used instead.
+ * (FP64 rounding), or n > 400, that interpolant is used instead.
  * ovl_sign_create: lam_max must bound |spectrum(H_w)| from above and lam_lo
  *   bound |lambda| from below on the subspace the polynomial acts on (with
  *   low modes: |lambda_l|).  n > 0 fixes the order; n = 0 picks the
  *   smallest n whose measured delta = max |1 - sqrt(x) P(x)| (400000 points
- *   of [eps,1]) is <= delta.  Takes ~0.2 s for a fixed n ~ 120 and 1-2 s
- *   for an order search.  OVL_E_ARG unless 0 < lam_lo < lam_max.
+ *   of [eps,1]) is <= delta.  Takes ~0.2-0.7 s for a fixed n and 0.5-15 s
+ *   for an order search (longest just below order 400, where the optimal
+ *   polynomial is searched one order at a time).  OVL_E_ARG unless
+ *   0 < lam_lo < lam_max.
  * ovl_sign_info: order n, eps and the measured delta.
  * ovl_sign_coeffs: copies c_0..c_n (n+1 doubles; cap = buffer length).
  */

@@ -27,8 +27,8 @@ Readings:
   until it alternates with equal size there and nowhere exceeds it.  When
   the interpolant's delta is already at the level of FP64 rounding
   (<= 1e-12) the extrema are noise and the interpolant is kept; so it is
-  above order 1000 (where the exchange's dense system gets large and the
-  two differ by a fraction of a per cent in order).  n is the
+  above order 400 (where the exchange's dense system gets large and the
+  two differ by a few per cent in order).  n is the
   order of P in x = Q^2, so one sign apply costs 2n+1 applications of D_w.
 * ||H_w|| is an upper bound lam_max on |spectrum(H_w)|, supplied as data.
 * With low modes, sqrt(eps) = |lambda_l| / lam_max (Sec. V).
@@ -154,7 +154,7 @@ def interpolant_order(eps: float, delta: float, npts: int = 400_000, n_max: int 
 # The optimal polynomial of eq. (4): Remez exchange
 # ---------------------------------------------------------------------------
 ROUNDING_DELTA = 1e-12  # below this the interpolant is kept (see Readings)
-MINIMAX_MAX_ORDER = 1000  # above this too (the dense (n+2)^2 exchange system)
+MINIMAX_MAX_ORDER = 400  # above this too (the dense (n+2)^2 exchange system)
 
 
 def relative_error(c: np.ndarray, eps: float, x) -> np.ndarray:

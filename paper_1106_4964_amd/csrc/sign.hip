@@ -98,12 +98,12 @@ double sign_delta(const std::vector<double>& c, double eps, int npts = 400000) {
 // included (golden-section search).  The start is the Chebyshev
 // interpolant, whose error vanishes at its n+1 nodes.  Kept instead of the
 // exchange: the interpolant itself when its delta is at the level of FP64
-// rounding (<= 1e-12, nothing left to level) or the order is above 1000
+// rounding (<= 1e-12, nothing left to level) or the order is above 400
 // (the dense (n+2)^2 system), and whenever the exchange ends worse.
 namespace {
 
 constexpr double kRoundingDelta = 1e-12;
-constexpr int kMinimaxMaxOrder = 1000;
+constexpr int kMinimaxMaxOrder = 400;
 
 double cheb_value(const std::vector<double>& c, double y) {
   double b1 = 0.0, b2 = 0.0;
