@@ -52,8 +52,8 @@ PROFILED_TRAFFIC = {
     (0, (2, 128, 0, 0, 8)): 2698047488,
     (3, (2, 256, 0, 0, 4)): 3534860288,
     (0, (2, 256, 0, 0, 4)): 2486437888,
-    (3, (2, 256, 0, 0, 8)): 3575134208,
-    (0, (2, 256, 0, 0, 8)): 2627336192,
+    (3, (2, 256, 0, 0, 8)): 3578030699,
+    (0, (2, 256, 0, 0, 8)): 2634959975,
 }
 
 
