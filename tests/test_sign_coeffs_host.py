@@ -30,7 +30,9 @@ def test_coefficients_match_oracle(lam_lo, lam_max, n):
     assert s.delta <= sign.measure_delta(sign.chebyshev_coefficients(eps, n), eps) + 1e-12
 
 
-@pytest.mark.parametrize("sq,delta", [(0.1, 1e-8)])
+# (0.1, 1e-8): the optimal polynomial, n = 84; (0.026, 1e-10): just above
+# the exchange's order limit of 400, where both keep the interpolant
+@pytest.mark.parametrize("sq,delta", [(0.1, 1e-8), (0.026, 1e-10)])
 def test_order_choice_matches_oracle(sq, delta):
     from paper_1106_4964_amd import ovl
 
